@@ -1,0 +1,180 @@
+/*
+ * brickcast.h -- C ABI of the bricked volume ray caster for one MI355X (gfx950).
+ *
+ * The calls follow the duties the paper gives each GPU's rendering thread
+ * (Section 2.2, item 5): load the data into GPU memory, take a rendering
+ * request made of the output frame size and the viewer's OpenGL projection
+ * and transformation matrices (Section 2.3.2), work out the rendering
+ * rectangle of the data and clip the ray casting to it (Section 2.3.2,
+ * Figure 4), ray cast, and hand the result over for compositing
+ * (Section 2.3.3).  Here one GPU holds a share of the cube split into bricks;
+ * each brick is ray cast into its own sub-image and the sub-images are
+ * composited front to back in visibility order.
+ *
+ * Conventions
+ *  - Every call returns an int32 status: BC_OK (0) or a negative BC_E_* code.
+ *    Nothing throws.  bc_last_error() gives the message of the last failure.
+ *  - Memory: the library never allocates device memory.  bc_plan() reports
+ *    the sizes of four device regions; the caller allocates them (PyTorch in
+ *    the Python binding) and passes them to bc_bind_memory().  The caller owns
+ *    them and must keep them alive until bc_destroy().  The library owns only
+ *    small host-side state (and a small pinned host buffer for per-frame
+ *    parameters).
+ *  - A context is bound to one HIP device and is not thread safe: one host
+ *    thread drives one context, as one CPU thread drives one GPU in the paper.
+ *  - Coordinates: voxel (i, j, k) of the global cube has its centre at
+ *    (i+1/2, j+1/2, k+1/2); source arrays are indexed data[z][y][x] with the
+ *    strides given in elements.  Image row 0 is the top row.
+ */
+#ifndef BRICKCAST_H
+#define BRICKCAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BC_OK = 0,
+  BC_E_ARG = -1,          /* invalid argument (message says which) */
+  BC_E_STATE = -2,        /* call out of order (e.g. render before load) */
+  BC_E_NOMEM = -3,        /* bound memory smaller than planned, or the frame
+                             needs more sub-image tiles than planned */
+  BC_E_HIP = -4,          /* HIP runtime failure; message holds hipGetErrorString */
+  BC_E_UNSUPPORTED = -5   /* valid but not supported by this build */
+};
+
+/* Storage form of the bricks in GPU memory. */
+enum bc_format {
+  BC_F32 = 0,             /* IEEE binary32 as given */
+  BC_F16 = 1,             /* IEEE binary16, round to nearest even */
+  BC_FP8_E4M3 = 2         /* OCP E4M3 with a per-brick scale s and offset o:
+                             v = q*s + o, o = (min+max)/2, s = (max-min)/896 over
+                             the brick's stored (core + ghost) values */
+};
+
+typedef struct bc_ctx bc_ctx;
+
+/* Create a context on HIP device `hip_device` (>= 0).  hip_device = -1 makes
+ * a host-only context that accepts bc_plan / bc_set_* (argument checking) but
+ * refuses every call that needs a GPU with BC_E_STATE.  *out is set to NULL on
+ * failure. */
+int bc_create(int hip_device, bc_ctx** out);
+
+/* Free library-owned host state.  Never frees caller memory.  NULL is a no-op. */
+void bc_destroy(bc_ctx* ctx);
+
+/* Message of the last failing call on ctx ("" if none).  Valid until the next
+ * call on ctx.  ctx may be NULL (then: message of the last bc_create failure). */
+const char* bc_last_error(const bc_ctx* ctx);
+
+/* The share of the cube this GPU renders and how it is bricked (Section 2.1,
+ * bricking; Section 2.3.1, the partition into sub-cubes). */
+typedef struct {
+  int64_t global_dims[3];   /* whole cube (x, y, z), voxels */
+  int64_t share_lo[3];      /* this GPU's share, half-open box [lo, hi) */
+  int64_t share_hi[3];
+  int32_t brick_dims[3];    /* brick edge (e.g. 64 or 256); edge bricks are truncated */
+  int32_t ghost;            /* ghost voxels per side; must be 1 */
+  int32_t storage;          /* enum bc_format */
+  int32_t src_dtype;        /* BC_F32 or BC_F16: element type of the source given to bc_load_bricks */
+} bc_volume_desc;
+
+/* Sizes (bytes) of the four device regions for a volume and the largest frame
+ * to be rendered:
+ *   bytes_out[0] brick pool     (bricks with ghosts, Z-order micro-blocks)
+ *   bytes_out[1] metadata       (brick table, views, order, rectangles, queue, counters, table)
+ *   bytes_out[2] sub-images     (max_tiles sub-image tiles of 8x8 RGBA float32)
+ *   bytes_out[3] load scratch   (one brick's source region, used when the source is on the host)
+ * max_tiles = 0 picks a default bound (views * screen tiles * (bricks along the
+ * three axes)).  Every region is 256-byte aligned by the caller.
+ * Errors: BC_E_ARG for null pointers, non-positive dims, a share outside the
+ * cube, ghost != 1, unknown storage/src_dtype, max_views not in [1, 4],
+ * max_w/max_h not in [1, 16384], more than 4096 bricks. */
+int bc_plan(bc_ctx* ctx, const bc_volume_desc* desc, int max_views, int max_w, int max_h,
+            int64_t max_tiles, size_t bytes_out[4]);
+
+/* Bind caller-allocated device memory (after bc_plan).  sizes[i] must be at
+ * least the planned bytes_out[i] (else BC_E_NOMEM); pointers must be 256-byte
+ * aligned device pointers on the context's device (else BC_E_ARG). */
+int bc_bind_memory(bc_ctx* ctx, void* const dev_ptrs[4], const size_t sizes[4]);
+
+/* Split the share into bricks with 1-voxel ghosts (clamp-replicated at the
+ * cube faces), compute per-brick minimum/maximum (the paper's min/max task,
+ * Section 2.3.1), encode to the storage form and lay the bricks out in GPU
+ * memory.  `src` covers the share plus its ghost halo clamped to the cube, the
+ * box [max(lo-1, 0), min(hi+1, N)), element type desc->src_dtype, strides in
+ * elements (x, y, z).  src_on_device != 0 means `src` is a device pointer on
+ * the context's device.  Synchronous: the caller may free or reuse `src` on
+ * return.  Errors: BC_E_STATE before bind; BC_E_ARG for a null src or strides
+ * smaller than the box rows/planes. */
+int bc_load_bricks(bc_ctx* ctx, const void* src, const int64_t src_strides[3], int src_on_device);
+
+/* Transfer function (Section 1.2: maps a voxel value to colour and opacity):
+ * K straight (not premultiplied) RGBA float entries in [0, 1], entry k at
+ * value vmin + k/(K-1) (vmax - vmin), opacity given per dt_ref voxels of ray
+ * length.  The table is copied.  Errors (BC_E_ARG): null rgba, K not in
+ * [2, 4096], vmin >= vmax or not finite, an entry outside [0, 1] or NaN,
+ * dt_ref <= 0. */
+int bc_set_transfer_function(bc_ctx* ctx, const float* rgba, int K, double vmin, double vmax,
+                             double dt_ref);
+
+/* One rendering request: the viewer's OpenGL matrices (column-major, as
+ * glGetDoublev returns them), the frame size, the sampling step along the ray
+ * in voxels and the early-ray-termination opacity (Section 2.3.2). */
+typedef struct {
+  double modelview[16];     /* rigid: [R t; 0 1] with R orthonormal (1e-9) */
+  double projection[16];    /* perspective (row 3 = 0 0 -1 0) or orthographic (row 3 = 0 0 0 1) */
+  int32_t width, height;
+  double step;              /* > 0, voxels */
+  double ert_threshold;     /* in (0, 1]; 1 disables early termination */
+} bc_view;
+
+/* Set 1..4 views rendered together by the next frames (one launch renders all
+ * of them).  All views must share width, height, step and ert_threshold, and
+ * fit the planned max_views/max_w/max_h.  Copied.  Errors: BC_E_ARG for the
+ * checks above; BC_E_NOMEM if the views' rendering rectangles need more
+ * sub-image tiles than planned. */
+int bc_set_view(bc_ctx* ctx, const bc_view* views, int n_views);
+
+/* Enqueue one frame on `stream` (a hipStream_t; NULL = the null stream) and
+ * return.  `out`: caller-owned device buffer of n_views*height*width*4
+ * float32, premultiplied RGBA, 16-byte aligned; pixels no brick covers are
+ * transparent black.  Errors (detected before anything is enqueued, `out`
+ * untouched): BC_E_STATE if memory, bricks, transfer function or view is
+ * missing; BC_E_ARG for a null or misaligned out. */
+int bc_render_frame(bc_ctx* ctx, float* out, void* stream);
+
+/* Statistics of the last frame; waits for it to finish. */
+typedef struct {
+  uint64_t nominal_samples;    /* samples composited, up to termination, skipped-empty ones included */
+  uint64_t evaluated_samples;  /* samples actually interpolated and looked up */
+  uint32_t n_tiles;            /* (brick, view, 8x8 tile) work items of the frame */
+  uint32_t reserved;
+} bc_frame_stats;
+int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);
+
+/* Brick table after bc_load_bricks: per brick the core box lo/hi (6 int32,
+ * global voxel coordinates) and the FP8 (scale, offset) (1, 0 otherwise),
+ * and the (min, max) of its stored values.  Any of the output arrays may be
+ * NULL.  *n receives the brick count; at most cap entries are written. */
+int bc_get_bricks(bc_ctx* ctx, int32_t* lo_hi, float* scale_offset, float* min_max, int cap, int* n);
+
+/* Visibility order (front to back brick indices) and rendering rectangles
+ * (x0, y0, x1, y1 half-open pixel bounds, already widened to whole 8x8 tiles)
+ * of `view` in the last frame; waits for it to finish. */
+int bc_get_visibility_order(bc_ctx* ctx, int view, int32_t* order, int cap);
+int bc_get_rects(bc_ctx* ctx, int view, int32_t* rects, int cap);
+
+/* Copy the stored elements of brick `b` (ghosted, padded to a multiple of 4
+ * per axis, 4x4x4 micro-blocks in row-major order, voxels inside a
+ * micro-block in Morton order) to host memory `dst` of `cap` bytes, and report
+ * the padded dims.  For tests of the layout and the encoders. */
+int bc_read_brick(bc_ctx* ctx, int b, void* dst, size_t cap, int32_t padded_dims[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BRICKCAST_H */

@@ -160,10 +160,11 @@ def sample_count(t_in, t_out, dt, hit):
 
 
 # ------------------------------------------------------------------ trilinear
-def trilinear(vol, p, origin=(0, 0, 0), clamp_dims=None):
+def trilinear(vol, p, origin=(0, 0, 0), decode=None):
     """Trilinear value at positions p (..., 3) of the array vol[z][y][x] whose
     element [0,0,0] is voxel ``origin`` (its centre at origin + 1/2).  Corner
-    indices are clamped to [0, n-1] of the array (C3)."""
+    indices are clamped to [0, n-1] of the array (C3).  ``decode`` maps the
+    gathered stored elements to FP64 values (storage forms)."""
     nz, ny, nx = vol.shape
     u = p - 0.5 - np.asarray(origin, dtype=np.float64)
     i0 = np.floor(u)
@@ -180,7 +181,9 @@ def trilinear(vol, p, origin=(0, 0, 0), clamp_dims=None):
     for cz, wz in ((0, 1.0 - fz), (1, fz)):
         for cy, wy in ((0, 1.0 - fy), (1, fy)):
             for cx, wx in ((0, 1.0 - fx), (1, fx)):
-                v = v + (wz * wy * wx) * vol[idx[2][cz], idx[1][cy], idx[0][cx]]
+                g = vol[idx[2][cz], idx[1][cy], idx[0][cx]]
+                g = decode(g) if decode is not None else g.astype(np.float64)
+                v = v + (wz * wy * wx) * g
     return v
 
 
@@ -269,31 +272,46 @@ def ghosted_region(vol, brick, ghost=1):
 
 @dataclass
 class StoredBrick:
+    """What one brick stores.  ``values`` is an array whose element [0,0,0] is
+    voxel ``origin``; for FP32/FP16 storage every brick shares the (rounded)
+    global cube, whose clamped edges are exactly the clamp-replicated ghosts;
+    FP8 bricks hold their own ghosted codes, decoded with the brick's own
+    scale and offset."""
     brick: Brick
-    values: np.ndarray       # FP64 decoded ghosted values
+    values: np.ndarray
+    origin: tuple
     scale: float = 1.0
     offset: float = 0.0
     codes: np.ndarray | None = None
 
+    def decode(self, g):
+        if self.codes is None:
+            return g.astype(np.float64)
+        return _E4M3_LUT[g] * self.scale + self.offset
+
+
+_E4M3_LUT = encoders.e4m3_value(np.arange(256))
+
 
 def store_bricks(vol, bricks, storage="f32", ghost=1):
-    """What each brick stores, decoded to FP64: f32 as given, f16 after an RNE
-    cast, fp8 after per-brick affine e4m3 quantisation (ghosts carry the
-    owning brick's quantisation)."""
+    """What each brick stores: f32 as given, f16 after an RNE cast, fp8 after
+    per-brick affine e4m3 quantisation over its core + ghost values (ghosts
+    carry the owning brick's quantisation)."""
     out = []
+    if storage == "f32":
+        shared = np.asarray(vol, dtype=np.float32)
+        return [StoredBrick(b, shared, (0, 0, 0)) for b in bricks]
+    if storage == "f16":
+        shared = encoders.f16_value(encoders.f16_bits(vol)).astype(np.float32)   # exact
+        return [StoredBrick(b, shared, (0, 0, 0)) for b in bricks]
+    if storage != "fp8":
+        raise ValueError(storage)
     for b in bricks:
         g = ghosted_region(vol, b, ghost).astype(np.float32)
-        if storage == "f32":
-            out.append(StoredBrick(b, g.astype(np.float64)))
-        elif storage == "f16":
-            bits = encoders.f16_bits(g)
-            out.append(StoredBrick(b, encoders.f16_value(bits), codes=bits))
-        elif storage == "fp8":
-            s, o = encoders.brick_scale_offset(float(g.min()), float(g.max()))
-            codes = encoders.fp8_encode_brick(g, s, o)
-            out.append(StoredBrick(b, encoders.fp8_decode_brick(codes, s, o), float(s), float(o), codes))
-        else:
-            raise ValueError(storage)
+        s, o = encoders.brick_scale_offset(float(g.min()), float(g.max()))
+        codes = encoders.fp8_encode_brick(g, s, o)
+        origin = tuple(int(x) - ghost for x in b.lo)
+        out.append(StoredBrick(b, codes, origin, float(s), float(o), codes))
     return out
 
 
@@ -434,7 +452,7 @@ def render_bricked(stored, dims, cam: Camera, tf: TransferFunction, dt: float, t
             p = o[:, None, :] + np.where(valid, t, 0.0)[..., None] * d[:, None, :]
             lo = np.asarray(sb.brick.lo)
             pc = np.where(valid[..., None], p, lo + 0.5)
-            v = trilinear(sb.values, pc, origin=tuple(int(x) - 1 for x in sb.brick.lo))
+            v = trilinear(sb.values, pc, origin=sb.origin, decode=sb.decode)
             c = tf.lookup(table, v)
             S, u, tt = composite(c, valid, tau)
             tie[s:e] |= tt
@@ -496,7 +514,7 @@ def _march_ray(stored_sorted, dims, o, d, table, tf, dt, tau, forced):
             continue
         ts = np.array([t_in + (j + 0.5) * dt for j in members])
         p = o[None, :] + ts[:, None] * d[None, :]
-        v = trilinear(sb.values, p, origin=tuple(int(x) - 1 for x in br.lo))
+        v = trilinear(sb.values, p, origin=sb.origin, decode=sb.decode)
         c = tf.lookup(table, v)
         S = np.zeros(4)
         for m, j in enumerate(members):

@@ -1,0 +1,255 @@
+"""Python binding of the brickcast C ABI (``include/brickcast.h``).
+
+Argument marshalling only: every step of the ray caster runs in the HIP
+library.  PyTorch provides the device memory the library asks for and the
+stream frames are enqueued on.  There is no fallback: if the library has not
+been built, :func:`load_library` raises :class:`LibraryMissing`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbrickcast.so")
+
+BC_OK, BC_E_ARG, BC_E_STATE, BC_E_NOMEM, BC_E_HIP, BC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+FORMATS = {"f32": 0, "f16": 1, "fp8": 2}
+SRC_DTYPES = {"f32": 0, "f16": 1}
+
+EXPORTS = [
+    "bc_create", "bc_destroy", "bc_last_error", "bc_plan", "bc_bind_memory", "bc_load_bricks",
+    "bc_set_transfer_function", "bc_set_view", "bc_render_frame", "bc_get_frame_stats",
+    "bc_get_bricks", "bc_get_visibility_order", "bc_get_rects", "bc_read_brick",
+]
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class BrickcastError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"brickcast error {code}: {msg}")
+        self.code = code
+
+
+class VolumeDesc(C.Structure):
+    _fields_ = [("global_dims", C.c_int64 * 3), ("share_lo", C.c_int64 * 3), ("share_hi", C.c_int64 * 3),
+                ("brick_dims", C.c_int32 * 3), ("ghost", C.c_int32), ("storage", C.c_int32),
+                ("src_dtype", C.c_int32)]
+
+
+class View(C.Structure):
+    _fields_ = [("modelview", C.c_double * 16), ("projection", C.c_double * 16), ("width", C.c_int32),
+                ("height", C.c_int32), ("step", C.c_double), ("ert_threshold", C.c_double)]
+
+
+class FrameStats(C.Structure):
+    _fields_ = [("nominal_samples", C.c_uint64), ("evaluated_samples", C.c_uint64),
+                ("n_tiles", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise LibraryMissing(f"{path} is not built; run `python -m paper_1205_0282_amd.build`")
+    lib = C.CDLL(path)
+    P, I, I64, D, F = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_float
+    sig = {
+        "bc_create": (I, [I, C.POINTER(P)]),
+        "bc_destroy": (None, [P]),
+        "bc_last_error": (C.c_char_p, [P]),
+        "bc_plan": (I, [P, C.POINTER(VolumeDesc), I, I, I, I64, C.POINTER(C.c_size_t)]),
+        "bc_bind_memory": (I, [P, C.POINTER(P), C.POINTER(C.c_size_t)]),
+        "bc_load_bricks": (I, [P, P, C.POINTER(C.c_int64), I]),
+        "bc_set_transfer_function": (I, [P, C.POINTER(F), I, D, D, D]),
+        "bc_set_view": (I, [P, C.POINTER(View), I]),
+        "bc_render_frame": (I, [P, P, P]),
+        "bc_get_frame_stats": (I, [P, C.POINTER(FrameStats)]),
+        "bc_get_bricks": (I, [P, C.POINTER(C.c_int32), C.POINTER(F), C.POINTER(F), I, C.POINTER(I)]),
+        "bc_get_visibility_order": (I, [P, I, C.POINTER(C.c_int32), I]),
+        "bc_get_rects": (I, [P, I, C.POINTER(C.c_int32), I]),
+        "bc_read_brick": (I, [P, I, P, C.c_size_t, C.POINTER(C.c_int32)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _view_struct(v) -> View:
+    s = View()
+    s.modelview[:] = [float(x) for x in np.asarray(v.modelview, dtype=np.float64).reshape(16)]
+    s.projection[:] = [float(x) for x in np.asarray(v.projection, dtype=np.float64).reshape(16)]
+    s.width, s.height = int(v.width), int(v.height)
+    s.step, s.ert_threshold = float(v.step), float(v.ert)
+    return s
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class BrickCaster:
+    """One context on one GPU: plan, bind (torch-allocated), load, set the
+    transfer function and views, render."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = C.c_void_p()
+        rc = self.lib.bc_create(device, C.byref(h))
+        if rc != BC_OK:
+            raise BrickcastError(rc, self.lib.bc_last_error(None).decode())
+        self.h = h
+        self.regions = None
+        self.n_views = 0
+        self.width = self.height = 0
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, rc):
+        if rc != BC_OK:
+            raise BrickcastError(rc, self.lib.bc_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bc_destroy(self.h)
+            self.h = None
+        self.regions = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- plan
+    def plan(self, global_dims, brick_dims, storage="f32", src_dtype="f32", share=None,
+             max_views=1, max_w=1920, max_h=1080, max_tiles=0):
+        d = VolumeDesc()
+        d.global_dims[:] = [int(x) for x in global_dims]
+        lo, hi = share if share is not None else ((0, 0, 0), tuple(global_dims))
+        d.share_lo[:] = [int(x) for x in lo]
+        d.share_hi[:] = [int(x) for x in hi]
+        d.brick_dims[:] = [int(x) for x in brick_dims]
+        d.ghost = 1
+        d.storage = FORMATS[storage] if isinstance(storage, str) else int(storage)
+        d.src_dtype = SRC_DTYPES[src_dtype] if isinstance(src_dtype, str) else int(src_dtype)
+        sizes = (C.c_size_t * 4)()
+        self._check(self.lib.bc_plan(self.h, C.byref(d), max_views, max_w, max_h, int(max_tiles), sizes))
+        self.desc = d
+        self.storage = storage
+        self.src_dtype = src_dtype
+        self.planned_sizes = [int(s) for s in sizes]
+        return self.planned_sizes
+
+    def bind(self):
+        import torch
+        dev = torch.device("cuda", self.device)
+        self.regions = [torch.empty(max(s, 256), dtype=torch.uint8, device=dev) for s in self.planned_sizes]
+        ptrs = (C.c_void_p * 4)(*[r.data_ptr() for r in self.regions])
+        sizes = (C.c_size_t * 4)(*[r.numel() for r in self.regions])
+        self._check(self.lib.bc_bind_memory(self.h, ptrs, sizes))
+
+    # ---------------------------------------------------------------- load
+    def load(self, volume):
+        """volume: numpy array (host) or torch tensor (device), [z][y][x],
+        covering the share plus its ghost halo clamped to the cube."""
+        import torch
+        if isinstance(volume, torch.Tensor):
+            assert volume.is_cuda and volume.dtype == (torch.float32 if self.src_dtype == "f32" else torch.float16)
+            strides = (C.c_int64 * 3)(volume.stride(2), volume.stride(1), volume.stride(0))
+            self._check(self.lib.bc_load_bricks(self.h, C.c_void_p(volume.data_ptr()), strides, 1))
+        else:
+            v = np.asarray(volume)
+            assert v.dtype == (np.float32 if self.src_dtype == "f32" else np.float16)
+            es = v.itemsize
+            strides = (C.c_int64 * 3)(v.strides[2] // es, v.strides[1] // es, v.strides[0] // es)
+            self._check(self.lib.bc_load_bricks(self.h, C.c_void_p(v.ctypes.data), strides, 0))
+
+    # ------------------------------------------------------------ requests
+    def set_transfer_function(self, rgba, vmin, vmax, dt_ref=1.0):
+        t = np.ascontiguousarray(rgba, dtype=np.float32)
+        self._check(self.lib.bc_set_transfer_function(self.h, _ptr(t, C.c_float), t.shape[0],
+                                                      float(vmin), float(vmax), float(dt_ref)))
+
+    def set_views(self, views):
+        arr = (View * len(views))(*[_view_struct(v) for v in views])
+        self._check(self.lib.bc_set_view(self.h, arr, len(views)))
+        self.n_views = len(views)
+        self.width, self.height = int(views[0].width), int(views[0].height)
+
+    def render(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.n_views, self.height, self.width, 4), dtype=torch.float32,
+                              device=torch.device("cuda", self.device))
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self.lib.bc_render_frame(self.h, C.c_void_p(out.data_ptr()), C.c_void_p(st)))
+        return out
+
+    # ------------------------------------------------------------- queries
+    def stats(self):
+        s = FrameStats()
+        self._check(self.lib.bc_get_frame_stats(self.h, C.byref(s)))
+        return {"nominal_samples": int(s.nominal_samples), "evaluated_samples": int(s.evaluated_samples),
+                "n_tiles": int(s.n_tiles)}
+
+    def bricks(self):
+        n = C.c_int()
+        self._check(self.lib.bc_get_bricks(self.h, None, None, None, 0, C.byref(n)))
+        lohi = np.zeros((n.value, 6), np.int32)
+        so = np.zeros((n.value, 2), np.float32)
+        mm = np.zeros((n.value, 2), np.float32)
+        self._check(self.lib.bc_get_bricks(self.h, _ptr(lohi, C.c_int32), _ptr(so, C.c_float),
+                                           _ptr(mm, C.c_float), n.value, C.byref(n)))
+        return lohi, so, mm
+
+    def visibility_order(self, view=0):
+        n = self.bricks()[0].shape[0]
+        o = np.zeros(n, np.int32)
+        self._check(self.lib.bc_get_visibility_order(self.h, view, _ptr(o, C.c_int32), n))
+        return o
+
+    def rects(self, view=0):
+        n = self.bricks()[0].shape[0]
+        r = np.zeros((n, 4), np.int32)
+        self._check(self.lib.bc_get_rects(self.h, view, _ptr(r, C.c_int32), n))
+        return r
+
+    def read_brick(self, b):
+        dims = (C.c_int32 * 3)()
+        self._check(self.lib.bc_read_brick(self.h, b, None, 0, dims))
+        gx, gy, gz = dims[0], dims[1], dims[2]
+        dt = {"f32": np.float32, "f16": np.uint16, "fp8": np.uint8}[self.storage]
+        buf = np.zeros(gx * gy * gz, dtype=dt)
+        self._check(self.lib.bc_read_brick(self.h, b, C.c_void_p(buf.ctypes.data), buf.nbytes, dims))
+        return buf, (gx, gy, gz)
+
+
+def unswizzle(buf, padded_dims):
+    """Stored brick elements (4x4x4 micro-blocks, Morton inside) -> array [z][y][x]
+    of the padded ghosted brick.  For layout tests."""
+    gx, gy, gz = padded_dims
+    mbx, mby, mbz = gx // 4, gy // 4, gz // 4
+    e = np.arange(gx * gy * gz)
+    mbi, inn = e >> 6, e & 63
+    wx = (inn & 1) | ((inn >> 2) & 2)
+    wy = ((inn >> 1) & 1) | ((inn >> 3) & 2)
+    wz = ((inn >> 2) & 1) | ((inn >> 4) & 2)
+    x = (mbi % mbx) * 4 + wx
+    y = ((mbi // mbx) % mby) * 4 + wy
+    z = (mbi // (mbx * mby)) * 4 + wz
+    out = np.zeros((gz, gy, gx), dtype=buf.dtype)
+    out[z, y, x] = buf
+    return out

@@ -1,0 +1,648 @@
+// Host runtime of the bricked ray caster: argument checking, memory planning,
+// brick loading, per-frame parameter upload and kernel sequencing.
+// The declarations and the contract of every entry point are in
+// include/brickcast.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/brickcast.h"
+#include "bc_kernels.h"
+#include "bc_types.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct bc_ctx {
+  int device = -1;
+  std::string err;
+  int n_cu = 256;
+  // plan
+  bool planned = false, bound = false, loaded = false, has_tf = false, has_view = false;
+  bc_volume_desc desc{};
+  int max_views = 0, max_w = 0, max_h = 0;
+  int64_t max_tiles = 0;
+  int nb[3] = {0, 0, 0};
+  int n_bricks = 0;
+  std::vector<BcBrick> bricks;
+  size_t elem_bytes = 4, src_elem_bytes = 4;
+  size_t bytes[4] = {0, 0, 0, 0};
+  size_t off_bricks = 0, off_fin = 0, off_views = 0, off_order = 0, off_rects = 0, off_item_base = 0,
+         off_ctr = 0;
+  void* dev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // per-frame input ring (pinned host memory) and events
+  BcFrameIn* pinned[2] = {nullptr, nullptr};
+  hipEvent_t copy_done[2] = {nullptr, nullptr};
+  bool copy_pending[2] = {false, false};
+  int ring = 0;
+  hipEvent_t frame_done = nullptr;
+  bool frame_pending = false;
+  int frame_views = 0;
+  // host-source load staging (pinned)
+  void* load_staging = nullptr;
+  size_t load_staging_bytes = 0;
+  // transfer function and views (host copies)
+  std::vector<float> tf;
+  int K = 0;
+  double vmin = 0, vmax = 1, dt_ref = 1;
+  std::vector<bc_view> views;
+  // kernel launch shape
+  int render_workgroups = 0;
+};
+
+namespace {
+
+int fail(bc_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHECK(c, expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail((c), BC_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+// row-major 4x4 from OpenGL column-major
+void rowmajor(const double* cm, double* rm) {
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) rm[r * 4 + c] = cm[c * 4 + r];
+}
+
+double det4(const double* m) {
+  // Laplace expansion over 2x2 minors
+  const double s0 = m[0] * m[5] - m[4] * m[1], s1 = m[0] * m[6] - m[4] * m[2];
+  const double s2 = m[0] * m[7] - m[4] * m[3], s3 = m[1] * m[6] - m[5] * m[2];
+  const double s4 = m[1] * m[7] - m[5] * m[3], s5 = m[2] * m[7] - m[6] * m[3];
+  const double c5 = m[10] * m[15] - m[14] * m[11], c4 = m[9] * m[15] - m[13] * m[11];
+  const double c3 = m[9] * m[14] - m[13] * m[10], c2 = m[8] * m[15] - m[12] * m[11];
+  const double c1 = m[8] * m[14] - m[12] * m[10], c0 = m[8] * m[13] - m[12] * m[9];
+  return s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0;
+}
+
+int check_view(bc_ctx* c, const bc_view& v, int idx) {
+  if (v.width < 1 || v.height < 1 || v.width > 16384 || v.height > 16384)
+    return fail(c, BC_E_ARG, "view %d: width/height %d x %d outside [1, 16384]", idx, v.width, v.height);
+  if (!(is_fin(v.step) && v.step > 0.0)) return fail(c, BC_E_ARG, "view %d: step must be finite and > 0", idx);
+  if (!(v.ert_threshold > 0.0 && v.ert_threshold <= 1.0))
+    return fail(c, BC_E_ARG, "view %d: ert_threshold must be in (0, 1]", idx);
+  double M[16], P[16];
+  rowmajor(v.modelview, M);
+  rowmajor(v.projection, P);
+  for (int k = 0; k < 16; ++k)
+    if (!is_fin(M[k]) || !is_fin(P[k])) return fail(c, BC_E_ARG, "view %d: non-finite matrix entry", idx);
+  if (!(M[12] == 0.0 && M[13] == 0.0 && M[14] == 0.0 && M[15] == 1.0))
+    return fail(c, BC_E_ARG, "view %d: modelview bottom row must be (0, 0, 0, 1)", idx);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += M[i * 4 + k] * M[j * 4 + k];
+      if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-9)
+        return fail(c, BC_E_ARG, "view %d: modelview rotation is not orthonormal", idx);
+    }
+  const bool persp = P[12] == 0.0 && P[13] == 0.0 && P[14] == -1.0 && P[15] == 0.0;
+  const bool ortho = P[12] == 0.0 && P[13] == 0.0 && P[14] == 0.0 && P[15] == 1.0;
+  if (!persp && !ortho)
+    return fail(c, BC_E_ARG, "view %d: projection is neither perspective nor orthographic", idx);
+  if (!(std::fabs(det4(P)) > 0.0)) return fail(c, BC_E_ARG, "view %d: projection is singular", idx);
+  return BC_OK;
+}
+
+// host bound on the tiles one view needs: the same rectangle as the device
+// setup, widened by one tile per side
+int64_t view_tiles_bound(const bc_ctx* c, const bc_view& v) {
+  double M[16], P[16], PM[16];
+  rowmajor(v.modelview, M);
+  rowmajor(v.projection, P);
+  for (int r = 0; r < 4; ++r)
+    for (int col = 0; col < 4; ++col) {
+      double s = 0.0;
+      for (int k = 0; k < 4; ++k) s += P[r * 4 + k] * M[k * 4 + col];
+      PM[r * 4 + col] = s;
+    }
+  const bool persp = P[14] == -1.0;
+  double eye[3];
+  for (int a = 0; a < 3; ++a) eye[a] = -((M[a] * M[3] + M[4 + a] * M[7]) + M[8 + a] * M[11]);
+  const int W = v.width, H = v.height;
+  const int TX = (W + BC_TILE - 1) / BC_TILE, TY = (H + BC_TILE - 1) / BC_TILE;
+  int64_t total = 0;
+  for (const BcBrick& b : c->bricks) {
+    bool full = false;
+    if (persp) {
+      bool inside = true;
+      for (int a = 0; a < 3; ++a) inside = inside && eye[a] >= b.lo[a] - 1 && eye[a] <= b.hi[a] + 1;
+      full = inside;
+    }
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    for (int k = 0; k < 8 && !full; ++k) {
+      const double X = (k & 1) ? b.hi[0] : b.lo[0], Y = (k & 2) ? b.hi[1] : b.lo[1], Z = (k & 4) ? b.hi[2] : b.lo[2];
+      double cl[4];
+      for (int i = 0; i < 4; ++i) cl[i] = PM[i * 4] * X + PM[i * 4 + 1] * Y + PM[i * 4 + 2] * Z + PM[i * 4 + 3];
+      if (!(cl[3] > 1e-12)) { full = true; break; }
+      const double px = (cl[0] / cl[3] + 1.0) * 0.5 * W - 0.5, py = (1.0 - cl[1] / cl[3]) * 0.5 * H - 0.5;
+      xmin = std::min(xmin, px); xmax = std::max(xmax, px);
+      ymin = std::min(ymin, py); ymax = std::max(ymax, py);
+    }
+    if (full) { total += (int64_t)TX * TY; continue; }
+    if (xmax < -2.0 || ymax < -2.0 || xmin > W + 1.0 || ymin > H + 1.0) continue;
+    const int x0 = (int)std::max(std::floor(xmin) - 1.0, 0.0), y0 = (int)std::max(std::floor(ymin) - 1.0, 0.0);
+    const int x1 = (int)std::min(std::ceil(xmax) + 1.0, (double)(W - 1)), y1 = (int)std::min(std::ceil(ymax) + 1.0, (double)(H - 1));
+    if (x1 < x0 || y1 < y0) continue;
+    const int tx0 = std::max(x0 / BC_TILE - 1, 0), ty0 = std::max(y0 / BC_TILE - 1, 0);
+    const int tx1 = std::min(x1 / BC_TILE + 2, TX), ty1 = std::min(y1 / BC_TILE + 2, TY);
+    total += (int64_t)(tx1 - tx0) * (ty1 - ty0);
+  }
+  return total;
+}
+
+BcFramePtrs frame_ptrs(bc_ctx* c) {
+  char* meta = static_cast<char*>(c->dev[1]);
+  BcFramePtrs f;
+  f.fin = reinterpret_cast<const BcFrameIn*>(meta + c->off_fin);
+  f.views = reinterpret_cast<BcViewParams*>(meta + c->off_views);
+  f.bricks = reinterpret_cast<const BcBrick*>(meta + c->off_bricks);
+  f.order = reinterpret_cast<int32_t*>(meta + c->off_order);
+  f.rects = reinterpret_cast<int32_t*>(meta + c->off_rects);
+  f.item_base = reinterpret_cast<int32_t*>(meta + c->off_item_base);
+  f.ctr = reinterpret_cast<BcCounters*>(meta + c->off_ctr);
+  f.sub = static_cast<float4*>(c->dev[2]);
+  f.pool = c->dev[0];
+  f.n_bricks = c->n_bricks;
+  f.n_views = c->frame_views;
+  for (int a = 0; a < 3; ++a) f.gdims[a] = (int32_t)c->desc.global_dims[a];
+  f.max_items = c->max_tiles;
+  f.storage = c->desc.storage;
+  f.width = c->views.empty() ? 0 : c->views[0].width;
+  f.height = c->views.empty() ? 0 : c->views[0].height;
+  return f;
+}
+
+int wait_frame(bc_ctx* c) {
+  if (c->frame_pending) {
+    HIPCHECK(c, hipEventSynchronize(c->frame_done));
+  }
+  return BC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bc_create(int hip_device, bc_ctx** out) {
+  if (!out) { g_create_error = "bc_create: out is NULL"; return BC_E_ARG; }
+  *out = nullptr;
+  if (hip_device < -1) { g_create_error = "bc_create: device must be >= -1"; return BC_E_ARG; }
+  bc_ctx* c = new bc_ctx();
+  c->device = hip_device;
+  if (hip_device >= 0) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || hip_device >= n) {
+      g_create_error = std::string("bc_create: no HIP device ") + std::to_string(hip_device) + ": " +
+                       (e != hipSuccess ? hipGetErrorString(e) : "index out of range");
+      delete c;
+      return BC_E_HIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipSetDevice(hip_device) != hipSuccess || hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
+      g_create_error = "bc_create: cannot query device";
+      delete c;
+      return BC_E_HIP;
+    }
+    c->n_cu = prop.multiProcessorCount;
+    c->render_workgroups = c->n_cu * 8;
+    bool ok = true;
+    for (int i = 0; i < 2 && ok; ++i) {
+      ok = hipHostMalloc(reinterpret_cast<void**>(&c->pinned[i]), sizeof(BcFrameIn), hipHostMallocDefault) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&c->copy_done[i], hipEventDisableTiming) == hipSuccess;
+    }
+    ok = ok && hipEventCreateWithFlags(&c->frame_done, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      g_create_error = "bc_create: cannot allocate pinned frame buffers / events";
+      bc_destroy(c);
+      return BC_E_HIP;
+    }
+  }
+  *out = c;
+  return BC_OK;
+}
+
+void bc_destroy(bc_ctx* c) {
+  if (!c) return;
+  if (c->device >= 0) {
+    (void)hipSetDevice(c->device);
+    if (c->frame_pending) (void)hipEventSynchronize(c->frame_done);
+    for (int i = 0; i < 2; ++i) {
+      if (c->copy_done[i]) (void)hipEventDestroy(c->copy_done[i]);
+      if (c->pinned[i]) (void)hipHostFree(c->pinned[i]);
+    }
+    if (c->frame_done) (void)hipEventDestroy(c->frame_done);
+    if (c->load_staging) (void)hipHostFree(c->load_staging);
+  }
+  delete c;
+}
+
+const char* bc_last_error(const bc_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int max_h, int64_t max_tiles,
+            size_t bytes_out[4]) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!d || !bytes_out) return fail(c, BC_E_ARG, "bc_plan: null desc or bytes_out");
+  for (int a = 0; a < 3; ++a) {
+    if (d->global_dims[a] < 1 || d->global_dims[a] > (1 << 20))
+      return fail(c, BC_E_ARG, "bc_plan: global_dims[%d] = %lld outside [1, 2^20]", a, (long long)d->global_dims[a]);
+    if (d->share_lo[a] < 0 || d->share_hi[a] > d->global_dims[a] || d->share_lo[a] >= d->share_hi[a])
+      return fail(c, BC_E_ARG, "bc_plan: share [%lld, %lld) on axis %d is empty or outside the cube",
+                  (long long)d->share_lo[a], (long long)d->share_hi[a], a);
+    if (d->brick_dims[a] < 4 || d->brick_dims[a] > 1024)
+      return fail(c, BC_E_ARG, "bc_plan: brick_dims[%d] = %d outside [4, 1024]", a, d->brick_dims[a]);
+  }
+  if (d->ghost != 1) return fail(c, BC_E_ARG, "bc_plan: ghost must be 1");
+  if (d->storage < 0 || d->storage > 2) return fail(c, BC_E_ARG, "bc_plan: unknown storage %d", d->storage);
+  if (d->src_dtype != BC_F32 && d->src_dtype != BC_F16)
+    return fail(c, BC_E_ARG, "bc_plan: src_dtype must be BC_F32 or BC_F16");
+  if (max_views < 1 || max_views > BC_MAX_VIEWS) return fail(c, BC_E_ARG, "bc_plan: max_views must be in [1, 4]");
+  if (max_w < 1 || max_h < 1 || max_w > 16384 || max_h > 16384)
+    return fail(c, BC_E_ARG, "bc_plan: max_w/max_h outside [1, 16384]");
+  if (max_tiles < 0) return fail(c, BC_E_ARG, "bc_plan: max_tiles must be >= 0");
+  int nb[3];
+  int64_t nbt = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t ext = d->share_hi[a] - d->share_lo[a];
+    nb[a] = (int)((ext + d->brick_dims[a] - 1) / d->brick_dims[a]);
+    nbt *= nb[a];
+  }
+  if (nbt > BC_MAX_BRICKS) return fail(c, BC_E_ARG, "bc_plan: %lld bricks exceed the limit of %d", (long long)nbt, BC_MAX_BRICKS);
+  if (c->bound) return fail(c, BC_E_STATE, "bc_plan: memory already bound to this context");
+  c->desc = *d;
+  c->max_views = max_views;
+  c->max_w = max_w;
+  c->max_h = max_h;
+  for (int a = 0; a < 3; ++a) c->nb[a] = nb[a];
+  c->n_bricks = (int)nbt;
+  c->elem_bytes = d->storage == BC_F32 ? 4 : (d->storage == BC_F16 ? 2 : 1);
+  c->src_elem_bytes = d->src_dtype == BC_F32 ? 4 : 2;
+  c->bricks.assign(c->n_bricks, BcBrick{});
+  int64_t off = 0;
+  size_t max_region = 0;
+  for (int bz = 0; bz < nb[2]; ++bz)
+    for (int by = 0; by < nb[1]; ++by)
+      for (int bx = 0; bx < nb[0]; ++bx) {
+        BcBrick& b = c->bricks[bx + nb[0] * (by + nb[1] * bz)];
+        const int bi[3] = {bx, by, bz};
+        int64_t region = 1;
+        for (int a = 0; a < 3; ++a) {
+          b.lo[a] = (int32_t)(d->share_lo[a] + (int64_t)bi[a] * d->brick_dims[a]);
+          b.hi[a] = (int32_t)std::min<int64_t>(b.lo[a] + d->brick_dims[a], d->share_hi[a]);
+          b.gdim[a] = ((b.hi[a] - b.lo[a] + 2) + 3) / 4 * 4;
+          b.mb[a] = b.gdim[a] / 4;
+          region *= (b.hi[a] - b.lo[a] + 2);
+        }
+        b.offset = off;
+        b.scale = 1.0f;
+        b.offs = 0.0f;
+        off += (int64_t)b.gdim[0] * b.gdim[1] * b.gdim[2];
+        max_region = std::max(max_region, (size_t)region);
+      }
+  const int64_t tiles_frame = (int64_t)((max_w + BC_TILE - 1) / BC_TILE) * ((max_h + BC_TILE - 1) / BC_TILE);
+  if (max_tiles == 0)
+    max_tiles = (int64_t)max_views * tiles_frame * std::min<int64_t>(nbt, (int64_t)nb[0] + nb[1] + nb[2] + 1);
+  c->max_tiles = max_tiles;
+  c->bytes[0] = align256((size_t)off * c->elem_bytes);
+  size_t m = 0;
+  c->off_bricks = m; m = align256(m + sizeof(BcBrick) * c->n_bricks);
+  c->off_fin = m; m = align256(m + sizeof(BcFrameIn));
+  c->off_views = m; m = align256(m + sizeof(BcViewParams) * BC_MAX_VIEWS);
+  c->off_order = m; m = align256(m + sizeof(int32_t) * BC_MAX_VIEWS * c->n_bricks);
+  c->off_rects = m; m = align256(m + sizeof(int32_t) * 4 * BC_MAX_VIEWS * c->n_bricks);
+  c->off_item_base = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
+  c->off_ctr = m; m = align256(m + sizeof(BcCounters));
+  c->bytes[1] = m;
+  c->bytes[2] = align256((size_t)max_tiles * BC_TILE * BC_TILE * 16);
+  c->bytes[3] = align256(max_region * c->src_elem_bytes);
+  for (int i = 0; i < 4; ++i) bytes_out[i] = c->bytes[i];
+  c->planned = true;
+  c->loaded = false;
+  return BC_OK;
+}
+
+int bc_bind_memory(bc_ctx* c, void* const ptrs[4], const size_t sizes[4]) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (c->device < 0) return fail(c, BC_E_STATE, "bc_bind_memory: host-only context");
+  if (!c->planned) return fail(c, BC_E_STATE, "bc_bind_memory: call bc_plan first");
+  if (!ptrs || !sizes) return fail(c, BC_E_ARG, "bc_bind_memory: null arrays");
+  for (int i = 0; i < 4; ++i) {
+    if (!ptrs[i]) return fail(c, BC_E_ARG, "bc_bind_memory: region %d is NULL", i);
+    if (reinterpret_cast<uintptr_t>(ptrs[i]) & 255) return fail(c, BC_E_ARG, "bc_bind_memory: region %d not 256-byte aligned", i);
+    if (sizes[i] < c->bytes[i])
+      return fail(c, BC_E_NOMEM, "bc_bind_memory: region %d has %zu bytes, %zu planned", i, sizes[i], c->bytes[i]);
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, ptrs[i]) != hipSuccess || attr.type != hipMemoryTypeDevice || attr.device != c->device) {
+      (void)hipGetLastError();
+      return fail(c, BC_E_ARG, "bc_bind_memory: region %d is not device memory on device %d", i, c->device);
+    }
+  }
+  HIPCHECK(c, hipSetDevice(c->device));
+  for (int i = 0; i < 4; ++i) c->dev[i] = ptrs[i];
+  char* meta = static_cast<char*>(c->dev[1]);
+  HIPCHECK(c, hipMemcpy(meta + c->off_bricks, c->bricks.data(), sizeof(BcBrick) * c->n_bricks, hipMemcpyHostToDevice));
+  c->bound = true;
+  c->loaded = false;
+  return BC_OK;
+}
+
+int bc_load_bricks(bc_ctx* c, const void* src, const int64_t strides[3], int src_on_device) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!c->bound) return fail(c, BC_E_STATE, "bc_load_bricks: bind memory first");
+  if (!src || !strides) return fail(c, BC_E_ARG, "bc_load_bricks: null src or strides");
+  const bc_volume_desc& d = c->desc;
+  int64_t box_lo[3], box_hi[3];
+  for (int a = 0; a < 3; ++a) {
+    box_lo[a] = std::max<int64_t>(d.share_lo[a] - 1, 0);
+    box_hi[a] = std::min<int64_t>(d.share_hi[a] + 1, d.global_dims[a]);
+  }
+  const int64_t ex = box_hi[0] - box_lo[0], ey = box_hi[1] - box_lo[1];
+  if (strides[0] < 1 || strides[1] < ex * strides[0] || strides[2] < ey * strides[1])
+    return fail(c, BC_E_ARG, "bc_load_bricks: strides (%lld, %lld, %lld) smaller than the source box rows/planes",
+                (long long)strides[0], (long long)strides[1], (long long)strides[2]);
+  HIPCHECK(c, hipSetDevice(c->device));
+  (void)wait_frame(c);
+  char* meta = static_cast<char*>(c->dev[1]);
+  BcBrick* dbricks = reinterpret_cast<BcBrick*>(meta + c->off_bricks);
+  BcCounters* ctr = reinterpret_cast<BcCounters*>(meta + c->off_ctr);
+  hipStream_t st = nullptr;
+  HIPCHECK(c, bc_launch_init_minmax(ctr, c->n_bricks, st));
+  for (int b = 0; b < c->n_bricks; ++b) {
+    const BcBrick& hb = c->bricks[b];
+    BcLoadSrc s;
+    s.dtype = d.src_dtype == BC_F32 ? 0 : 1;
+    for (int a = 0; a < 3; ++a) s.dims[a] = (int32_t)d.global_dims[a];
+    if (src_on_device) {
+      s.ptr = src;
+      for (int a = 0; a < 3; ++a) {
+        s.strides[a] = strides[a];
+        s.origin[a] = (int32_t)box_lo[a];
+      }
+    } else {
+      // gather the brick's ghosted region (clamped to the cube) into pinned
+      // staging, then copy it into the scratch region
+      int64_t rlo[3], rhi[3];
+      for (int a = 0; a < 3; ++a) {
+        rlo[a] = std::max<int64_t>(hb.lo[a] - 1, 0);
+        rhi[a] = std::min<int64_t>(hb.hi[a] + 1, d.global_dims[a]);
+      }
+      const int64_t rx = rhi[0] - rlo[0], ry = rhi[1] - rlo[1], rz = rhi[2] - rlo[2];
+      const size_t need = (size_t)(rx * ry * rz) * c->src_elem_bytes;
+      if (need > c->bytes[3]) return fail(c, BC_E_NOMEM, "bc_load_bricks: scratch region too small");
+      if (c->load_staging_bytes < need) {
+        if (c->load_staging) (void)hipHostFree(c->load_staging);
+        c->load_staging = nullptr;
+        HIPCHECK(c, hipHostMalloc(&c->load_staging, c->bytes[3], hipHostMallocDefault));
+        c->load_staging_bytes = c->bytes[3];
+      }
+      const char* base = static_cast<const char*>(src);
+      char* dst = static_cast<char*>(c->load_staging);
+      const size_t eb = c->src_elem_bytes;
+      for (int64_t z = 0; z < rz; ++z)
+        for (int64_t y = 0; y < ry; ++y) {
+          const char* row = base + (((rlo[2] + z - box_lo[2]) * strides[2] + (rlo[1] + y - box_lo[1]) * strides[1] +
+                                     (rlo[0] - box_lo[0]) * strides[0]) * eb);
+          char* o = dst + ((z * ry + y) * rx) * eb;
+          if (strides[0] == 1) {
+            std::memcpy(o, row, rx * eb);
+          } else {
+            for (int64_t x = 0; x < rx; ++x) std::memcpy(o + x * eb, row + x * strides[0] * eb, eb);
+          }
+        }
+      HIPCHECK(c, hipMemcpy(c->dev[3], c->load_staging, need, hipMemcpyHostToDevice));
+      s.ptr = c->dev[3];
+      s.strides[0] = 1;
+      s.strides[1] = rx;
+      s.strides[2] = rx * ry;
+      for (int a = 0; a < 3; ++a) s.origin[a] = (int32_t)rlo[a];
+    }
+    HIPCHECK(c, bc_launch_minmax(s, hb.lo, hb.hi, ctr, b, st));
+    HIPCHECK(c, bc_launch_finalize(dbricks, ctr, b, 1, d.storage, st));
+    const int64_t n_elems = (int64_t)hb.gdim[0] * hb.gdim[1] * hb.gdim[2];
+    HIPCHECK(c, bc_launch_encode(s, dbricks, b, n_elems, d.storage, c->dev[0], st));
+    if (!src_on_device) HIPCHECK(c, hipStreamSynchronize(st));
+  }
+  HIPCHECK(c, hipStreamSynchronize(st));
+  HIPCHECK(c, hipMemcpy(c->bricks.data(), dbricks, sizeof(BcBrick) * c->n_bricks, hipMemcpyDeviceToHost));
+  c->loaded = true;
+  return BC_OK;
+}
+
+int bc_set_transfer_function(bc_ctx* c, const float* rgba, int K, double vmin, double vmax, double dt_ref) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!rgba) return fail(c, BC_E_ARG, "bc_set_transfer_function: rgba is NULL");
+  if (K < 2 || K > BC_MAX_K) return fail(c, BC_E_ARG, "bc_set_transfer_function: K = %d outside [2, %d]", K, BC_MAX_K);
+  if (!is_fin(vmin) || !is_fin(vmax) || !(vmin < vmax))
+    return fail(c, BC_E_ARG, "bc_set_transfer_function: need finite vmin < vmax");
+  if (!(is_fin(dt_ref) && dt_ref > 0.0)) return fail(c, BC_E_ARG, "bc_set_transfer_function: dt_ref must be > 0");
+  for (int i = 0; i < 4 * K; ++i)
+    if (!(rgba[i] >= 0.0f && rgba[i] <= 1.0f))
+      return fail(c, BC_E_ARG, "bc_set_transfer_function: entry %d channel %d = %g outside [0, 1]", i / 4, i % 4, (double)rgba[i]);
+  c->tf.assign(rgba, rgba + 4 * K);
+  c->K = K;
+  c->vmin = vmin;
+  c->vmax = vmax;
+  c->dt_ref = dt_ref;
+  c->has_tf = true;
+  return BC_OK;
+}
+
+int bc_set_view(bc_ctx* c, const bc_view* views, int n) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!views) return fail(c, BC_E_ARG, "bc_set_view: views is NULL");
+  if (n < 1 || n > BC_MAX_VIEWS) return fail(c, BC_E_ARG, "bc_set_view: n_views = %d outside [1, 4]", n);
+  if (c->planned && n > c->max_views) return fail(c, BC_E_ARG, "bc_set_view: %d views exceed the planned %d", n, c->max_views);
+  for (int i = 0; i < n; ++i) {
+    int r = check_view(c, views[i], i);
+    if (r) return r;
+    if (views[i].width != views[0].width || views[i].height != views[0].height || views[i].step != views[0].step ||
+        views[i].ert_threshold != views[0].ert_threshold)
+      return fail(c, BC_E_ARG, "bc_set_view: all views must share width, height, step and ert_threshold");
+    if (c->planned && (views[i].width > c->max_w || views[i].height > c->max_h))
+      return fail(c, BC_E_ARG, "bc_set_view: frame %d x %d exceeds the planned %d x %d", views[i].width,
+                  views[i].height, c->max_w, c->max_h);
+  }
+  if (c->planned) {
+    int64_t tiles = 0;
+    for (int i = 0; i < n; ++i) tiles += view_tiles_bound(c, views[i]);
+    if (tiles > c->max_tiles)
+      return fail(c, BC_E_NOMEM, "bc_set_view: the views need up to %lld sub-image tiles, %lld planned",
+                  (long long)tiles, (long long)c->max_tiles);
+  }
+  c->views.assign(views, views + n);
+  c->has_view = true;
+  return BC_OK;
+}
+
+int bc_render_frame(bc_ctx* c, float* out, void* stream) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (c->device < 0) return fail(c, BC_E_STATE, "bc_render_frame: host-only context");
+  if (!c->bound || !c->loaded) return fail(c, BC_E_STATE, "bc_render_frame: bricks not loaded");
+  if (!c->has_tf) return fail(c, BC_E_STATE, "bc_render_frame: no transfer function");
+  if (!c->has_view) return fail(c, BC_E_STATE, "bc_render_frame: no view");
+  if (!out) return fail(c, BC_E_ARG, "bc_render_frame: out is NULL");
+  if (reinterpret_cast<uintptr_t>(out) & 15) return fail(c, BC_E_ARG, "bc_render_frame: out not 16-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHECK(c, hipSetDevice(c->device));
+  const int slot = c->ring;
+  c->ring ^= 1;
+  if (c->copy_pending[slot]) HIPCHECK(c, hipEventSynchronize(c->copy_done[slot]));
+  BcFrameIn* fin = c->pinned[slot];
+  const int n = (int)c->views.size();
+  for (int i = 0; i < n; ++i) {
+    BcViewIn& vi = fin->views[i];
+    std::memcpy(vi.mv, c->views[i].modelview, sizeof vi.mv);
+    std::memcpy(vi.pr, c->views[i].projection, sizeof vi.pr);
+    vi.width = c->views[i].width;
+    vi.height = c->views[i].height;
+    vi.step = c->views[i].step;
+    vi.tau = c->views[i].ert_threshold;
+  }
+  fin->n_views = n;
+  fin->K = c->K;
+  const double dt = c->views[0].step;
+  const double scale = (c->K - 1) / (c->vmax - c->vmin);
+  fin->tf_scale = (float)scale;
+  fin->tf_bias = (float)(-c->vmin * scale);
+  for (int k = 0; k < c->K; ++k) {
+    const double a = c->tf[4 * k + 3];
+    const double ac = 1.0 - std::pow(1.0 - a, dt / c->dt_ref);
+    fin->table[k][0] = (float)(ac * c->tf[4 * k + 0]);
+    fin->table[k][1] = (float)(ac * c->tf[4 * k + 1]);
+    fin->table[k][2] = (float)(ac * c->tf[4 * k + 2]);
+    fin->table[k][3] = (float)ac;
+  }
+  const size_t bytes = offsetof(BcFrameIn, table) + sizeof(float) * 4 * c->K;
+  char* meta = static_cast<char*>(c->dev[1]);
+  HIPCHECK(c, hipMemcpyAsync(meta + c->off_fin, fin, bytes, hipMemcpyHostToDevice, st));
+  HIPCHECK(c, hipEventRecord(c->copy_done[slot], st));
+  c->copy_pending[slot] = true;
+  c->frame_views = n;
+  BcFramePtrs f = frame_ptrs(c);
+  HIPCHECK(c, bc_launch_setup(f, st));
+  HIPCHECK(c, bc_launch_render(f, c->render_workgroups, st));
+  HIPCHECK(c, bc_launch_composite(f, reinterpret_cast<float4*>(out), st));
+  HIPCHECK(c, hipEventRecord(c->frame_done, st));
+  c->frame_pending = true;
+  return BC_OK;
+}
+
+int bc_get_frame_stats(bc_ctx* c, bc_frame_stats* s) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!s) return fail(c, BC_E_ARG, "bc_get_frame_stats: stats is NULL");
+  if (!c->frame_pending) return fail(c, BC_E_STATE, "bc_get_frame_stats: no frame rendered");
+  HIPCHECK(c, hipSetDevice(c->device));
+  int r = wait_frame(c);
+  if (r) return r;
+  char* meta = static_cast<char*>(c->dev[1]);
+  BcCounters h;
+  HIPCHECK(c, hipMemcpy(&h, meta + c->off_ctr, offsetof(BcCounters, minmax), hipMemcpyDeviceToHost));
+  s->nominal_samples = h.nominal;
+  s->evaluated_samples = h.evaluated;
+  s->n_tiles = h.n_items;
+  s->reserved = 0;
+  return BC_OK;
+}
+
+int bc_get_bricks(bc_ctx* c, int32_t* lo_hi, float* so, float* mm, int cap, int* n) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!c->planned) return fail(c, BC_E_STATE, "bc_get_bricks: call bc_plan first");
+  if (cap < 0) return fail(c, BC_E_ARG, "bc_get_bricks: cap < 0");
+  if (n) *n = c->n_bricks;
+  const int m = std::min(cap, c->n_bricks);
+  for (int b = 0; b < m; ++b) {
+    const BcBrick& br = c->bricks[b];
+    if (lo_hi)
+      for (int a = 0; a < 3; ++a) {
+        lo_hi[b * 6 + a] = br.lo[a];
+        lo_hi[b * 6 + 3 + a] = br.hi[a];
+      }
+    if (so) { so[2 * b] = br.scale; so[2 * b + 1] = br.offs; }
+    if (mm) { mm[2 * b] = br.vmin; mm[2 * b + 1] = br.vmax; }
+  }
+  return BC_OK;
+}
+
+int bc_get_visibility_order(bc_ctx* c, int view, int32_t* order, int cap) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!order) return fail(c, BC_E_ARG, "bc_get_visibility_order: order is NULL");
+  if (!c->frame_pending) return fail(c, BC_E_STATE, "bc_get_visibility_order: no frame rendered");
+  if (view < 0 || view >= c->frame_views) return fail(c, BC_E_ARG, "bc_get_visibility_order: bad view %d", view);
+  if (cap < c->n_bricks) return fail(c, BC_E_ARG, "bc_get_visibility_order: cap %d < %d bricks", cap, c->n_bricks);
+  HIPCHECK(c, hipSetDevice(c->device));
+  int r = wait_frame(c);
+  if (r) return r;
+  char* meta = static_cast<char*>(c->dev[1]);
+  HIPCHECK(c, hipMemcpy(order, meta + c->off_order + sizeof(int32_t) * view * c->n_bricks,
+                        sizeof(int32_t) * c->n_bricks, hipMemcpyDeviceToHost));
+  return BC_OK;
+}
+
+int bc_get_rects(bc_ctx* c, int view, int32_t* rects, int cap) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!rects) return fail(c, BC_E_ARG, "bc_get_rects: rects is NULL");
+  if (!c->frame_pending) return fail(c, BC_E_STATE, "bc_get_rects: no frame rendered");
+  if (view < 0 || view >= c->frame_views) return fail(c, BC_E_ARG, "bc_get_rects: bad view %d", view);
+  if (cap < c->n_bricks) return fail(c, BC_E_ARG, "bc_get_rects: cap %d < %d bricks", cap, c->n_bricks);
+  HIPCHECK(c, hipSetDevice(c->device));
+  int r = wait_frame(c);
+  if (r) return r;
+  char* meta = static_cast<char*>(c->dev[1]);
+  HIPCHECK(c, hipMemcpy(rects, meta + c->off_rects + sizeof(int32_t) * 4 * view * c->n_bricks,
+                        sizeof(int32_t) * 4 * c->n_bricks, hipMemcpyDeviceToHost));
+  for (int b = 0; b < c->n_bricks; ++b)
+    for (int k = 0; k < 4; ++k) rects[4 * b + k] *= BC_TILE;
+  return BC_OK;
+}
+
+int bc_read_brick(bc_ctx* c, int b, void* dst, size_t cap, int32_t dims[3]) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!c->loaded) return fail(c, BC_E_STATE, "bc_read_brick: bricks not loaded");
+  if (b < 0 || b >= c->n_bricks) return fail(c, BC_E_ARG, "bc_read_brick: brick %d out of range", b);
+  const BcBrick& br = c->bricks[b];
+  const size_t bytes = (size_t)br.gdim[0] * br.gdim[1] * br.gdim[2] * c->elem_bytes;
+  if (dims)
+    for (int a = 0; a < 3; ++a) dims[a] = br.gdim[a];
+  if (!dst) return BC_OK;
+  if (cap < bytes) return fail(c, BC_E_ARG, "bc_read_brick: need %zu bytes", bytes);
+  HIPCHECK(c, hipSetDevice(c->device));
+  (void)wait_frame(c);
+  HIPCHECK(c, hipMemcpy(dst, static_cast<char*>(c->dev[0]) + br.offset * c->elem_bytes, bytes, hipMemcpyDeviceToHost));
+  return BC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+// Kernel launchers called by the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "bc_types.h"
+
+struct BcLoadSrc {
+  const void* ptr;        // device pointer
+  int64_t strides[3];     // elements (x, y, z)
+  int32_t origin[3];      // global voxel coordinates of element [0][0][0]
+  int32_t dims[3];        // global cube dims
+  int32_t dtype;          // 0 float32, 1 float16
+};
+
+hipError_t bc_launch_init_minmax(BcCounters* ctr, int n, hipStream_t st);
+hipError_t bc_launch_minmax(const BcLoadSrc& src, const int32_t lo[3], const int32_t hi[3],
+                            BcCounters* ctr, int b, hipStream_t st);
+hipError_t bc_launch_finalize(BcBrick* bricks, const BcCounters* ctr, int first, int count, int storage,
+                              hipStream_t st);
+hipError_t bc_launch_encode(const BcLoadSrc& src, const BcBrick* bricks, int b, int64_t n_elems,
+                            int storage, void* pool, hipStream_t st);
+
+struct BcFramePtrs {
+  const BcFrameIn* fin;
+  BcViewParams* views;
+  const BcBrick* bricks;
+  int32_t* order;         // [BC_MAX_VIEWS][n_bricks]
+  int32_t* rects;         // [BC_MAX_VIEWS][n_bricks][4] tiles (x0, y0, x1, y1)
+  int32_t* item_base;     // [n_bricks * n_views + 1]
+  BcCounters* ctr;
+  float4* sub;            // sub-image tiles: [max_items][64]
+  const void* pool;
+  int32_t n_bricks, n_views;
+  int32_t gdims[3];
+  int64_t max_items;
+  int32_t storage;
+  int32_t width, height;  // frame size (all views share it)
+};
+
+hipError_t bc_launch_setup(const BcFramePtrs& f, hipStream_t st);
+hipError_t bc_launch_render(const BcFramePtrs& f, int n_workgroups, hipStream_t st);
+hipError_t bc_launch_composite(const BcFramePtrs& f, float4* out, hipStream_t st);

@@ -1,0 +1,198 @@
+// Load-time kernels: per-brick minimum/maximum of the stored values (the
+// paper's min/max task after the data reaches GPU memory, Section 2.3.1), the
+// FP8 scale/offset, and the encode + layout of ghosted bricks into 4x4x4
+// micro-blocks (voxels of a micro-block in Morton order, micro-blocks
+// row-major inside the brick).
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include "bc_types.h"
+#include "bc_kernels.h"
+
+namespace {
+
+__device__ __forceinline__ uint32_t ordered_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float from_ordered(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+template <typename T> __device__ __forceinline__ float to_f32(T v);
+template <> __device__ __forceinline__ float to_f32<float>(float v) { return v; }
+template <> __device__ __forceinline__ float to_f32<__half>(__half v) { return __half2float(v); }
+
+struct SrcView {
+  const void* ptr;
+  int64_t sx, sy, sz;   // strides (elements)
+  int32_t ox, oy, oz;   // global voxel coordinates of element [0][0][0]
+  int32_t nx, ny, nz;   // global cube dims (for clamping)
+};
+
+template <typename T>
+__device__ __forceinline__ float src_at(const SrcView& s, int gx, int gy, int gz) {
+  gx = min(max(gx, 0), s.nx - 1);
+  gy = min(max(gy, 0), s.ny - 1);
+  gz = min(max(gz, 0), s.nz - 1);
+  const T* p = static_cast<const T*>(s.ptr);
+  return to_f32<T>(p[(int64_t)(gx - s.ox) * s.sx + (int64_t)(gy - s.oy) * s.sy + (int64_t)(gz - s.oz) * s.sz]);
+}
+
+// min/max over the brick's ghosted region [lo-1, hi+1) (clamped to the cube)
+template <typename T>
+__global__ __launch_bounds__(256) void minmax_kernel(SrcView s, int3 lo, int3 ext, uint32_t* out) {
+  const int64_t total = (int64_t)ext.x * ext.y * ext.z;
+  float mn = INFINITY, mx = -INFINITY;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(e % ext.x);
+    const int y = (int)((e / ext.x) % ext.y);
+    const int z = (int)(e / ((int64_t)ext.x * ext.y));
+    const float v = src_at<T>(s, lo.x - 1 + x, lo.y - 1 + y, lo.z - 1 + z);
+    mn = fminf(mn, v);
+    mx = fmaxf(mx, v);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = fminf(mn, __shfl_xor(mn, off));
+    mx = fmaxf(mx, __shfl_xor(mx, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&out[0], ordered_bits(mn));
+    atomicMax(&out[1], ordered_bits(mx));
+  }
+}
+
+__global__ void init_minmax_kernel(BcCounters* ctr, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    ctr->minmax[i][0] = 0xffffffffu;
+    ctr->minmax[i][1] = 0u;
+  }
+}
+
+// scale/offset of each brick from its stored range (FP32 formulas:
+// o = (min+max)/2, s = (max-min)/896, s = 1 when max == min)
+__global__ void finalize_kernel(BcBrick* bricks, const BcCounters* ctr, int first, int count, int storage) {
+  const int b = first + blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= first + count) return;
+  const float mn = from_ordered(ctr->minmax[b][0]);
+  const float mx = from_ordered(ctr->minmax[b][1]);
+  bricks[b].vmin = mn;
+  bricks[b].vmax = mx;
+  float s = 1.0f, o = 0.0f;
+  if (storage == 2) {
+    if (mx == mn) {
+      s = 1.0f;
+      o = mn;
+    } else {
+      o = (mn + mx) / 2.0f;
+      s = (mx - mn) / 896.0f;
+    }
+  }
+  bricks[b].scale = s;
+  bricks[b].offs = o;
+}
+
+// round to nearest even on the E4M3 grid, saturating at +-448
+__device__ __forceinline__ uint8_t encode_e4m3(float x) {
+  const uint32_t bits = __float_as_uint(x);
+  const uint32_t sign = (bits >> 31) << 7;
+  if (x != x) return (uint8_t)(sign | 0x7f);
+  float a = fminf(fabsf(x), 448.0f);
+  uint32_t code;
+  if (a < 0.015625f) {                               // below 2^-6: quantum 2^-9
+    code = (uint32_t)rintf(a * 512.0f);              // 0..8 (8 is the smallest normal)
+  } else {
+    int e = (int)((__float_as_uint(a) >> 23) & 255) - 127;   // 2^e <= a < 2^(e+1), e in [-6, 8]
+    float r = rintf(ldexpf(a, 3 - e));               // in [8, 16]
+    uint32_t m = (uint32_t)r;
+    if (m == 16) { m = 8; e += 1; }
+    code = ((uint32_t)(e + 7) << 3) | (m - 8);
+  }
+  return (uint8_t)(sign | code);
+}
+
+template <typename T, int FMT>
+__global__ __launch_bounds__(256) void encode_kernel(SrcView s, const BcBrick* bricks, int b, void* pool) {
+  const BcBrick br = bricks[b];
+  const int64_t total = (int64_t)br.gdim[0] * br.gdim[1] * br.gdim[2];
+  const int cx = br.hi[0] - br.lo[0], cy = br.hi[1] - br.lo[1], cz = br.hi[2] - br.lo[2];
+  const float inv = 1.0f / br.scale;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t mbi = e >> 6;
+    const int in = (int)(e & 63);
+    const int mbx = (int)(mbi % br.mb[0]);
+    const int mby = (int)((mbi / br.mb[0]) % br.mb[1]);
+    const int mbz = (int)(mbi / ((int64_t)br.mb[0] * br.mb[1]));
+    const int wx = (in & 1) | ((in >> 2) & 2);
+    const int wy = ((in >> 1) & 1) | ((in >> 3) & 2);
+    const int wz = ((in >> 2) & 1) | ((in >> 4) & 2);
+    // local ghosted index (0 <-> voxel lo-1); padding replicates the last ghost
+    const int lx = min(mbx * 4 + wx, cx + 1);
+    const int ly = min(mby * 4 + wy, cy + 1);
+    const int lz = min(mbz * 4 + wz, cz + 1);
+    const float v = src_at<T>(s, br.lo[0] - 1 + lx, br.lo[1] - 1 + ly, br.lo[2] - 1 + lz);
+    const int64_t dst = br.offset + e;
+    if (FMT == 0) {
+      static_cast<float*>(pool)[dst] = v;
+    } else if (FMT == 1) {
+      static_cast<__half*>(pool)[dst] = __float2half_rn(v);
+    } else {
+      const float xq = (v - br.offs) * inv;
+      static_cast<uint8_t*>(pool)[dst] = encode_e4m3(xq);
+    }
+  }
+}
+
+inline SrcView make_src(const BcLoadSrc& s) {
+  SrcView v;
+  v.ptr = s.ptr;
+  v.sx = s.strides[0]; v.sy = s.strides[1]; v.sz = s.strides[2];
+  v.ox = s.origin[0]; v.oy = s.origin[1]; v.oz = s.origin[2];
+  v.nx = s.dims[0]; v.ny = s.dims[1]; v.nz = s.dims[2];
+  return v;
+}
+
+}  // namespace
+
+hipError_t bc_launch_init_minmax(BcCounters* ctr, int n, hipStream_t st) {
+  init_minmax_kernel<<<(n + 255) / 256, 256, 0, st>>>(ctr, n);
+  return hipGetLastError();
+}
+
+hipError_t bc_launch_minmax(const BcLoadSrc& src, const int32_t lo[3], const int32_t hi[3],
+                            BcCounters* ctr, int b, hipStream_t st) {
+  SrcView s = make_src(src);
+  int3 l = make_int3(lo[0], lo[1], lo[2]);
+  int3 ext = make_int3(hi[0] - lo[0] + 2, hi[1] - lo[1] + 2, hi[2] - lo[2] + 2);
+  const int64_t total = (int64_t)ext.x * ext.y * ext.z;
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  if (src.dtype == 0)
+    minmax_kernel<float><<<grid, 256, 0, st>>>(s, l, ext, ctr->minmax[b]);
+  else
+    minmax_kernel<__half><<<grid, 256, 0, st>>>(s, l, ext, ctr->minmax[b]);
+  return hipGetLastError();
+}
+
+hipError_t bc_launch_finalize(BcBrick* bricks, const BcCounters* ctr, int first, int count, int storage,
+                              hipStream_t st) {
+  finalize_kernel<<<(count + 255) / 256, 256, 0, st>>>(bricks, ctr, first, count, storage);
+  return hipGetLastError();
+}
+
+hipError_t bc_launch_encode(const BcLoadSrc& src, const BcBrick* bricks, int b, int64_t n_elems,
+                            int storage, void* pool, hipStream_t st) {
+  SrcView s = make_src(src);
+  int grid = (int)std::min<int64_t>((n_elems + 255) / 256, 8192);
+  if (src.dtype == 0) {
+    if (storage == 0) encode_kernel<float, 0><<<grid, 256, 0, st>>>(s, bricks, b, pool);
+    else if (storage == 1) encode_kernel<float, 1><<<grid, 256, 0, st>>>(s, bricks, b, pool);
+    else encode_kernel<float, 2><<<grid, 256, 0, st>>>(s, bricks, b, pool);
+  } else {
+    if (storage == 0) encode_kernel<__half, 0><<<grid, 256, 0, st>>>(s, bricks, b, pool);
+    else if (storage == 1) encode_kernel<__half, 1><<<grid, 256, 0, st>>>(s, bricks, b, pool);
+    else encode_kernel<__half, 2><<<grid, 256, 0, st>>>(s, bricks, b, pool);
+  }
+  return hipGetLastError();
+}

@@ -1,0 +1,64 @@
+// Layouts shared by the host runtime and the kernels of the bricked ray caster.
+#pragma once
+#include <stdint.h>
+
+#define BC_MAX_VIEWS 4
+#define BC_MAX_BRICKS 4096
+#define BC_MAX_K 4096
+#define BC_TILE 8          // screen tile edge (pixels): one wave of 64 rays per work item
+#define BC_MB 4            // micro-block edge (voxels): 64 voxels stored contiguously
+
+// A rendering request as the viewer sends it (FP64, OpenGL column-major).
+struct BcViewIn {
+  double mv[16];
+  double pr[16];
+  int32_t width, height;
+  double step, tau;
+};
+
+// Per-frame input copied host -> device in one transfer before the frame.
+struct BcFrameIn {
+  BcViewIn views[BC_MAX_VIEWS];
+  int32_t n_views, K;
+  float tf_scale, tf_bias;   // table coordinate x = v * tf_scale + tf_bias
+  float table[BC_MAX_K][4];  // opacity-corrected premultiplied RGBA entries (only K used)
+};
+
+// Derived per-view quantities written by the FP64 setup kernel.  Vectors used
+// per ray are stored as double-float pairs (hi + lo) so that FP32 arithmetic
+// can place samples as accurately as FP64 would.
+struct BcViewParams {
+  int32_t kind;              // 0 perspective, 1 orthographic
+  int32_t width, height, tiles_x, tiles_y;
+  int32_t pad0;
+  float dt_hi, dt_lo;        // step (double-float)
+  float tau;
+  float pad1;
+  // perspective: e = eye, a/b/c: unnormalised direction u(x, y) = a x + b y + c
+  // orthographic: e = origin at NDC (0, 0) on the near plane, a/b its NDC
+  // derivatives, c = unit view direction
+  float e_hi[3], e_lo[3];
+  float a_hi[3], a_lo[3];
+  float b_hi[3], b_lo[3];
+  float c_hi[3], c_lo[3];
+  double eye[3];
+  double dir[3];
+  double pm[16];             // P*M, row-major
+};
+
+struct BcBrick {
+  int32_t lo[3], hi[3];      // core box, global voxel coordinates
+  int32_t gdim[3];           // stored dims: core + 2 ghosts, padded to a multiple of 4
+  int32_t mb[3];             // micro-blocks per axis
+  int64_t offset;            // first element of the brick in the pool
+  float scale, offs;         // decode v = q * scale + offs (FP8); 1, 0 otherwise
+  float vmin, vmax;          // range of the stored (core + ghost) values
+};
+
+struct BcCounters {
+  uint32_t n_items;          // work items of the frame
+  uint32_t queue;            // next work item (persistent kernel)
+  unsigned long long nominal;
+  unsigned long long evaluated;
+  uint32_t minmax[BC_MAX_BRICKS][2];   // load time: ordered-int min/max per brick
+};

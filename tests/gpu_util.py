@@ -1,0 +1,47 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C ABI and the
+oracle on the same seeded inputs, and compare under the near-tie rule."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import raycast as rc
+from paper_1205_0282_amd import binding, synth
+
+TOL = 2e-5   # max |GPU - oracle| per RGBA channel for FP32 arithmetic
+
+
+def cam_of(v: synth.ViewSpec) -> rc.Camera:
+    return rc.Camera(v.modelview, v.projection, v.width, v.height)
+
+
+def gpu_render(vol, brick, views, tf_rgba, vmin, vmax, storage="f32", src="device", max_tiles=0,
+               keep=False):
+    import torch
+    dims = vol.shape[::-1]
+    bc = binding.BrickCaster(0)
+    src_dtype = "f16" if vol.dtype == np.float16 else "f32"
+    bc.plan(dims, brick, storage=storage, src_dtype=src_dtype, max_views=len(views),
+            max_w=views[0].width, max_h=views[0].height, max_tiles=max_tiles)
+    bc.bind()
+    if src == "device":
+        t = torch.from_numpy(np.ascontiguousarray(vol)).cuda()
+        bc.load(t)
+        del t
+    else:
+        bc.load(np.ascontiguousarray(vol))
+    bc.set_transfer_function(tf_rgba, vmin, vmax)
+    bc.set_views(views)
+    out = bc.render()
+    torch.cuda.synchronize()
+    img = out.cpu().numpy().astype(np.float64)
+    if keep:
+        return img, bc
+    bc.close()
+    return img
+
+
+def compare(gpu_pixels, res: rc.RenderResult, tol=TOL):
+    """Returns (max error over pixels under the near-tie rule, n_tie, n_overflow)."""
+    err = rc.max_abs_with_branches(gpu_pixels, res)
+    ok = ~res.overflow
+    return float(err[ok].max()) if ok.any() else 0.0, int(res.tie.sum()), int(res.overflow.sum())

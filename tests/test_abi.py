@@ -1,0 +1,193 @@
+"""C ABI: the built library loads, exports every entry point the header
+declares, and rejects bad arguments and out-of-order calls on a host-only
+context (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1205_0282_amd import binding, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "brickcast.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert set(_declared()) == set(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+@pytest.fixture
+def host_ctx(lib):
+    h = C.c_void_p()
+    assert lib.bc_create(-1, C.byref(h)) == binding.BC_OK
+    yield h
+    lib.bc_destroy(h)
+
+
+def _desc(dims=(64, 64, 64), brick=(32, 32, 32), storage=0):
+    d = binding.VolumeDesc()
+    d.global_dims[:] = dims
+    d.share_lo[:] = (0, 0, 0)
+    d.share_hi[:] = dims
+    d.brick_dims[:] = brick
+    d.ghost = 1
+    d.storage = storage
+    d.src_dtype = 0
+    return d
+
+
+def _plan(lib, h, d, views=1, w=64, h_=64, tiles=0):
+    sizes = (C.c_size_t * 4)()
+    return lib.bc_plan(h, C.byref(d), views, w, h_, tiles, sizes), [int(s) for s in sizes]
+
+
+def test_create_rejects_bad_args(lib):
+    assert lib.bc_create(-1, None) == binding.BC_E_ARG
+    h = C.c_void_p()
+    assert lib.bc_create(-7, C.byref(h)) == binding.BC_E_ARG
+    assert h.value is None
+    assert b"device" in lib.bc_last_error(None)
+
+
+def test_plan_sizes(lib, host_ctx):
+    rc, sz = _plan(lib, host_ctx, _desc())
+    assert rc == 0
+    # 8 bricks of 32^3 -> ghosted 34 -> padded 36 per axis, 4 bytes each
+    assert sz[0] == 8 * 36 ** 3 * 4
+    assert sz[3] >= 34 ** 3 * 4
+    rc, sz16 = _plan(lib, host_ctx, _desc(storage=1))
+    assert rc == 0 and sz16[0] == 8 * 36 ** 3 * 2
+    rc, sz8 = _plan(lib, host_ctx, _desc(storage=2))
+    assert rc == 0 and sz8[0] == 8 * 36 ** 3
+    # uneven edge bricks: 70 = 32 + 32 + 6 -> padded 36, 36, 8
+    rc, szu = _plan(lib, host_ctx, _desc(dims=(70, 64, 64)))
+    assert rc == 0 and szu[0] == (2 * 36 + 8) * 36 * 36 * 2 * 2 * 4
+
+
+@pytest.mark.parametrize("field,value", [
+    ("global_dims", (0, 64, 64)), ("brick_dims", (2, 32, 32)), ("ghost", 2), ("storage", 7),
+    ("src_dtype", 2), ("share_hi", (65, 64, 64)), ("share_lo", (10, 0, 0))])
+def test_plan_rejects_bad_desc(lib, host_ctx, field, value):
+    d = _desc()
+    if field == "share_lo":
+        d.share_hi[:] = (10, 64, 64)
+    attr = getattr(d, field)
+    if isinstance(value, tuple):
+        attr[:] = value
+    else:
+        setattr(d, field, value)
+    rc, _ = _plan(lib, host_ctx, d)
+    assert rc == binding.BC_E_ARG
+    assert lib.bc_last_error(host_ctx)
+
+
+def test_plan_rejects_too_many_bricks_and_views(lib, host_ctx):
+    rc, _ = _plan(lib, host_ctx, _desc(dims=(1024, 1024, 1024), brick=(16, 16, 16)))
+    assert rc == binding.BC_E_ARG
+    rc, _ = _plan(lib, host_ctx, _desc(), views=5)
+    assert rc == binding.BC_E_ARG
+    rc, _ = _plan(lib, host_ctx, _desc(), w=0)
+    assert rc == binding.BC_E_ARG
+
+
+def _tf(lib, h, rgba, K=None, vmin=0.0, vmax=1.0, dt_ref=1.0):
+    a = np.ascontiguousarray(rgba, np.float32)
+    return lib.bc_set_transfer_function(h, a.ctypes.data_as(C.POINTER(C.c_float)),
+                                        a.shape[0] if K is None else K, vmin, vmax, dt_ref)
+
+
+def test_transfer_function_checks(lib, host_ctx):
+    good = np.full((8, 4), 0.5, np.float32)
+    assert _tf(lib, host_ctx, good) == 0
+    assert _tf(lib, host_ctx, good, K=1) == binding.BC_E_ARG
+    assert _tf(lib, host_ctx, np.full((4097, 4), 0.5)) == binding.BC_E_ARG
+    assert _tf(lib, host_ctx, good, vmin=1.0, vmax=1.0) == binding.BC_E_ARG
+    assert _tf(lib, host_ctx, good, vmin=float("nan")) == binding.BC_E_ARG
+    assert _tf(lib, host_ctx, good, dt_ref=0.0) == binding.BC_E_ARG
+    bad = good.copy(); bad[3, 2] = 1.5
+    assert _tf(lib, host_ctx, bad) == binding.BC_E_ARG
+    bad[3, 2] = np.nan
+    assert _tf(lib, host_ctx, bad) == binding.BC_E_ARG
+    assert lib.bc_set_transfer_function(host_ctx, None, 8, 0.0, 1.0, 1.0) == binding.BC_E_ARG
+
+
+def _views(*vs):
+    return (binding.View * len(vs))(*[binding._view_struct(v) for v in vs])
+
+
+def test_view_checks(lib, host_ctx):
+    v = synth.orbit_view((64, 64, 64), 3, kind="persp", width=64, height=48)
+    assert lib.bc_set_view(host_ctx, _views(v), 1) == 0
+    assert lib.bc_set_view(host_ctx, _views(v, v, v, v), 4) == 0
+    assert lib.bc_set_view(host_ctx, None, 1) == binding.BC_E_ARG
+    assert lib.bc_set_view(host_ctx, _views(v), 0) == binding.BC_E_ARG
+    assert lib.bc_set_view(host_ctx, _views(v, v, v, v, v), 5) == binding.BC_E_ARG
+    for mutate in ("scale", "proj", "step", "ert", "size", "nan", "mixed"):
+        w = synth.orbit_view((64, 64, 64), 3, kind="persp", width=64, height=48)
+        vs = [w]
+        if mutate == "scale":
+            w.modelview = w.modelview.copy(); w.modelview[0] *= 2.0
+        elif mutate == "proj":
+            w.projection = w.projection.copy(); w.projection[11] = -0.5
+        elif mutate == "step":
+            w.step = 0.0
+        elif mutate == "ert":
+            w.ert = 1.5
+        elif mutate == "size":
+            w.width = 0
+        elif mutate == "nan":
+            w.modelview = w.modelview.copy(); w.modelview[13] = np.nan
+        elif mutate == "mixed":
+            u = synth.orbit_view((64, 64, 64), 3, kind="persp", width=32, height=48)
+            vs = [w, u]
+        assert lib.bc_set_view(host_ctx, _views(*vs), len(vs)) == binding.BC_E_ARG, mutate
+        assert lib.bc_last_error(host_ctx)
+
+
+def test_view_tile_budget(lib, host_ctx):
+    d = _desc()
+    rc, _ = _plan(lib, host_ctx, d, views=1, w=64, h_=64, tiles=4)
+    assert rc == 0
+    v = synth.orbit_view((64, 64, 64), 3, kind="persp", width=64, height=64)
+    assert lib.bc_set_view(host_ctx, _views(v), 1) == binding.BC_E_NOMEM
+    rc, _ = _plan(lib, host_ctx, d, views=1, w=64, h_=64, tiles=0)
+    assert lib.bc_set_view(host_ctx, _views(v), 1) == 0
+
+
+def test_host_only_context_refuses_gpu_calls(lib, host_ctx):
+    rc, _ = _plan(lib, host_ctx, _desc())
+    assert rc == 0
+    ptrs = (C.c_void_p * 4)()
+    sizes = (C.c_size_t * 4)()
+    assert lib.bc_bind_memory(host_ctx, ptrs, sizes) == binding.BC_E_STATE
+    assert lib.bc_render_frame(host_ctx, None, None) == binding.BC_E_STATE
+    st = binding.FrameStats()
+    assert lib.bc_get_frame_stats(host_ctx, C.byref(st)) == binding.BC_E_STATE
+    strides = (C.c_int64 * 3)(1, 64, 64 * 64)
+    assert lib.bc_load_bricks(host_ctx, C.c_void_p(1), strides, 0) == binding.BC_E_STATE
+    assert lib.bc_read_brick(host_ctx, 0, None, 0, None) == binding.BC_E_STATE
+
+
+def test_get_bricks_after_plan(lib, host_ctx):
+    rc, _ = _plan(lib, host_ctx, _desc(dims=(70, 64, 40), brick=(32, 32, 32)))
+    assert rc == 0
+    n = C.c_int()
+    assert lib.bc_get_bricks(host_ctx, None, None, None, 0, C.byref(n)) == 0
+    assert n.value == 3 * 2 * 2
+    lohi = np.zeros((n.value, 6), np.int32)
+    assert lib.bc_get_bricks(host_ctx, lohi.ctypes.data_as(C.POINTER(C.c_int32)), None, None, n.value, C.byref(n)) == 0
+    from oracle import raycast as rc_
+    ref = rc_.brick_grid((70, 64, 40), (32, 32, 32))
+    assert np.array_equal(lohi, np.array([list(b.lo) + list(b.hi) for b in ref], np.int32))

@@ -1,0 +1,174 @@
+"""Parity of the HIP ray caster (through the C ABI) with the FP64 oracle on
+the same seeded inputs.  Images: max |GPU - oracle| <= 2e-5 per RGBA channel
+(near-tie rays may match any of their branches); brick order, brick table and
+encoded bricks bit-exact; rendering rectangles cover every pixel whose ray has
+a sample in the brick."""
+import numpy as np
+import pytest
+
+from oracle import encoders
+from oracle import raycast as rc
+from paper_1205_0282_amd import binding, synth
+
+from gpu_util import TOL, cam_of, compare, gpu_render
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small_cube():
+    return synth.make_cube(synth.RECIPE_SMALL, workers=4)
+
+
+def _ramp(vol):
+    vmin, vmax = float(vol.min()), float(vol.max())
+    return synth.ramp_tf(vmin, vmax), vmin, vmax
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.99])
+def test_small_plain_full_frame(small_cube, tau):
+    """128^3 cube, 2x2x2 bricks of 64^3, orthographic 256x256, step 0.5."""
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    v = synth.orbit_view(vol.shape[::-1], 7, kind="ortho", width=256, height=256, ert=tau)
+    img, bc = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax, keep=True)
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    stored = rc.store_bricks(vol, rc.brick_grid(vol.shape[::-1], (64, 64, 64)))
+    res = rc.render_bricked(stored, vol.shape[::-1], cam_of(v), tf, 0.5, tau)
+    err, n_tie, n_ovf = compare(img[0].reshape(-1, 4), res)
+    print(f"max err {err:.3g}, near-tie rays {n_tie}, overflow {n_ovf}")
+    assert err <= TOL
+    assert n_ovf == 0
+    assert res.image[:, 3].max() > 0.5           # the frame is not trivially empty
+    assert np.array_equal(bc.visibility_order(0), np.asarray(res.order, np.int32))
+    rects = bc.rects(0)
+    py, px = np.divmod(np.arange(256 * 256), 256)
+    for b, fp in res.footprint.items():
+        x0, y0, x1, y1 = rects[b]
+        assert np.all((px[fp] >= x0) & (px[fp] < x1) & (py[fp] >= y0) & (py[fp] < y1))
+    st = bc.stats()
+    assert abs(st["nominal_samples"] - int(res.samples.sum())) <= 64 * n_tie
+    bc.close()
+
+
+@pytest.mark.parametrize("n,brick,kind,seed", [
+    (8, (3, 5, 2), "persp", 1), (8, (8, 8, 8), "ortho", 2), (16, (5, 7, 6), "persp", 3),
+    (16, (16, 4, 9), "ortho", 4)])
+def test_brute_force_cubes_four_views(n, brick, kind, seed):
+    """Tiny random cubes with uneven bricks, four views in one launch."""
+    rng = np.random.default_rng(seed)
+    dims = (n, n + 1, n - 1)
+    vol = rng.uniform(-1, 1, dims[::-1]).astype(np.float32)
+    rgba = synth.random_tf(rng, 16, alpha_max=0.7)
+    views = [synth.orbit_view(dims, f, kind=kind, width=40, height=32, elevation_deg=25.0, step=0.37, ert=0.8)
+             for f in (3, 19, 35, 51)]
+    img, bc = gpu_render(vol, brick, views, rgba, -1.0, 1.0, keep=True)
+    tf = rc.TransferFunction(rgba, -1.0, 1.0)
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, brick))
+    for i, v in enumerate(views):
+        res = rc.render_bricked(stored, dims, cam_of(v), tf, 0.37, 0.8)
+        err, n_tie, n_ovf = compare(img[i].reshape(-1, 4), res)
+        assert err <= TOL, (i, err)
+        assert np.array_equal(bc.visibility_order(i), np.asarray(res.order, np.int32))
+    bc.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "fp8"])
+def test_stored_bricks_bit_exact(storage):
+    """GPU bricking, ghosts and encoders against the oracle's, element by element."""
+    rng = np.random.default_rng(11)
+    dims = (37, 29, 21)
+    vol = (rng.standard_normal(dims[::-1]) * 3).astype(np.float32)
+    bc = binding.BrickCaster(0)
+    bc.plan(dims, (16, 16, 8), storage=storage, max_w=16, max_h=16)
+    bc.bind()
+    bc.load(vol)
+    lohi, so, mm = bc.bricks()
+    bricks = rc.brick_grid(dims, (16, 16, 8))
+    for b in bricks:
+        g = rc.ghosted_region(vol, b)
+        buf, pdims = bc.read_brick(b.index)
+        arr = binding.unswizzle(buf, pdims)[:g.shape[0], :g.shape[1], :g.shape[2]]
+        assert list(lohi[b.index]) == list(b.lo) + list(b.hi)
+        assert mm[b.index, 0] == g.min() and mm[b.index, 1] == g.max()
+        if storage == "f32":
+            assert np.array_equal(arr, g)
+        elif storage == "f16":
+            assert np.array_equal(arr, encoders.f16_bits(g))
+        else:
+            s, o = encoders.brick_scale_offset(float(g.min()), float(g.max()))
+            assert so[b.index, 0] == s and so[b.index, 1] == o
+            assert np.array_equal(arr, encoders.fp8_encode_brick(g, s, o))
+    bc.close()
+
+
+@pytest.mark.parametrize("storage", ["f16", "fp8"])
+def test_precision_forms_match_oracle_on_stored_values(small_cube, storage):
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    v = synth.orbit_view(vol.shape[::-1], 21, kind="ortho", width=256, height=256, ert=0.99)
+    img = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax, storage=storage)
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    stored = rc.store_bricks(vol, rc.brick_grid(vol.shape[::-1], (64, 64, 64)), storage)
+    res = rc.render_bricked(stored, vol.shape[::-1], cam_of(v), tf, 0.5, 0.99)
+    err, n_tie, _ = compare(img[0].reshape(-1, 4), res)
+    assert err <= TOL, err
+    # and the error of the storage form against FP32 data, reported
+    ref = rc.render_bricked(rc.store_bricks(vol, rc.brick_grid(vol.shape[::-1], (64, 64, 64))),
+                            vol.shape[::-1], cam_of(v), tf, 0.5, 0.99)
+    print(storage, "max abs vs FP32 data", np.abs(img[0].reshape(-1, 4) - ref.image).max(),
+          "PSNR", rc.psnr(img[0].reshape(-1, 4), ref.image))
+
+
+def test_uneven_bricks_host_and_device_loads_agree():
+    rng = np.random.default_rng(12)
+    dims = (70, 50, 45)
+    base = synth.CubeRecipe(dims, seed=5, n_sources=8, sigma_lo=2, sigma_hi=6)
+    vol = synth.make_cube(base, workers=2)
+    rgba, vmin, vmax = _ramp(vol)
+    v = synth.orbit_view(dims, 40, kind="persp", width=96, height=80, ert=0.99)
+    a = gpu_render(vol, (32, 32, 32), [v], rgba, vmin, vmax, src="device")
+    b = gpu_render(vol, (32, 32, 32), [v], rgba, vmin, vmax, src="host")
+    assert np.array_equal(a, b)
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    res = rc.render_bricked(rc.store_bricks(vol, rc.brick_grid(dims, (32, 32, 32))), dims, cam_of(v), tf, 0.5, 0.99)
+    err, _, _ = compare(a[0].reshape(-1, 4), res)
+    assert err <= TOL
+
+
+def test_without_termination_equals_unbricked(small_cube):
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    v = synth.orbit_view(vol.shape[::-1], 50, kind="persp", width=160, height=120, ert=1.0)
+    img = gpu_render(vol, (48, 48, 48), [v], rgba, vmin, vmax)
+    res = rc.render_full(vol, cam_of(v), rc.TransferFunction(rgba, vmin, vmax), 0.5, 1.0)
+    err = np.abs(img[0].reshape(-1, 4) - res.image).max(axis=1)
+    assert err[~res.tie].max() <= TOL
+
+
+def test_degenerate_inputs(small_cube):
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    zero = rgba.copy()
+    zero[:, 3] = 0.0
+    v = synth.orbit_view(vol.shape[::-1], 9, kind="persp", width=64, height=48)
+    assert np.all(gpu_render(vol, (64, 64, 64), [v], zero, vmin, vmax) == 0.0)
+    # the cube behind the viewer: every pixel transparent
+    away = synth.orbit_view(vol.shape[::-1], 9, kind="persp", width=64, height=48)
+    M = rc.mat_from_col_major(away.modelview)
+    M[:3, :] = np.diag([-1.0, 1.0, -1.0]) @ M[:3, :]
+    away.modelview = np.ascontiguousarray(M.T).reshape(16)
+    assert np.all(gpu_render(vol, (64, 64, 64), [away], rgba, vmin, vmax) == 0.0)
+
+
+def test_batched_views_equal_single_views_and_repeat(small_cube):
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    views = [synth.orbit_view(vol.shape[::-1], f, kind="persp", width=120, height=90) for f in (0, 16, 32, 48)]
+    batch, bc = gpu_render(vol, (64, 64, 64), views, rgba, vmin, vmax, keep=True)
+    again = bc.render().cpu().numpy()
+    assert np.array_equal(again, batch.astype(np.float32))
+    bc.close()
+    for i, v in enumerate(views):
+        single = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax)
+        assert np.array_equal(single[0], batch[i])

@@ -420,11 +420,14 @@ def test_fp8_bricks_use_own_quantisation_and_fp16_is_exact_cast():
     bricks = rc.brick_grid(dims, (5, 4, 4))
     s16 = rc.store_bricks(vol, bricks, "f16")
     s8 = rc.store_bricks(vol, bricks, "fp8")
-    for a, b in zip(s16, s8):
-        g = rc.ghosted_region(vol, a.brick)
-        assert np.array_equal(a.values, g.astype(np.float16).astype(np.float64))
-        assert np.max(np.abs(b.values - g)) <= (g.max() - g.min()) / 896 * 16 + 1e-9
-        assert b.values.min() <= g.min() + 1e-6 and b.offset == np.float32((g.min() + g.max()) / 2)
+    assert np.array_equal(s16[0].values, vol.astype(np.float16).astype(np.float32))
+    for b in s8:
+        g = rc.ghosted_region(vol, b.brick)
+        dec = b.decode(b.codes)
+        assert dec.shape == g.shape
+        assert np.max(np.abs(dec - g)) <= (g.max() - g.min()) / 896 * 16 + 1e-9
+        assert b.offset == np.float32((np.float32(g.min()) + np.float32(g.max())) / np.float32(2))
+        assert b.origin == tuple(x - 1 for x in b.brick.lo)
 
 
 def test_branch_enumeration_consistent_with_vectorised_path():
