@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Frame-rate benchmark of the bricked ray caster on one MI355X.
+
+Workload (default): a 1024^3 float32 spectral-cube stand-in (N(0,1) noise plus
+500 Gaussian sources, 5% of voxels above 3), bricked into 4x4x4 bricks of
+256^3 voxels with 1-voxel ghosts, rendered perspective at 1920x1080 with a
+0.5-voxel step and early ray termination at opacity 0.99, over a 64-frame
+orbit.  One step is one frame of the whole per-frame path: the FP64 set-up
+(inverse view transform, visibility order, rendering rectangles, work list),
+the per-brick ray casting into sub-images, and the sort-last compositing into
+the output image.  The cube is resident in GPU memory before timing starts.
+
+Prints one JSON line.  ``value`` is nominal samples (samples composited up to
+early termination, empty-space-skipped ones included) per second over the
+timed frames, in Gsamples/s.  The roofline object refers to the ray-casting
+kernel; its algorithmic bytes per launch are the core voxels of every brick
+whose rendering rectangle is non-empty (each voxel read once) plus the
+sub-image tiles written (1 KiB per 8x8 tile).  ``cpu_baseline`` is the FP64
+oracle timed on a bounded random sample of the first frame's pixels, in
+processes forked over the host cores before the GPU is touched.
+
+    python bench.py [--gpus 1] [--steps 64] [--warmup 3] [--storage f32|f16|fp8]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+# the oracle's 4x4 products gain nothing from BLAS threads, and forked
+# oracle workers must not inherit a BLAS thread pool
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+
+import numpy as np  # noqa: E402
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1205_0282_amd import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+ORBIT = 64
+
+WORKLOADS = {
+    # name: (recipe, brick edge, width, height)
+    "cube1024_persp1920x1080": (synth.RECIPE_1024, 256, 1920, 1080),
+    "cube128_ortho256": (synth.RECIPE_SMALL, 64, 256, 256),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=ORBIT)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--storage", choices=("f32", "f16", "fp8"), default="f32")
+    p.add_argument("--workload", choices=sorted(WORKLOADS), default="cube1024_persp1920x1080")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="target wall time of the oracle sample (0 disables the CPU baseline)")
+    p.add_argument("--cpu-workers", type=int, default=0, help="0 = all host cores, at most 16")
+    return p.parse_args()
+
+
+def views_for(recipe, width, height):
+    kind = "persp" if width != height else "ortho"
+    return [synth.orbit_view(recipe.dims, k, ORBIT, kind=kind, width=width, height=height, step=0.5, ert=0.99)
+            for k in range(ORBIT)]
+
+
+# ------------------------------------------------------------------ CPU oracle
+_CPU = {}
+
+
+def _cpu_chunk(pix):
+    from oracle import raycast as rc
+    c = _CPU
+    t0 = time.perf_counter()
+    res = rc.render_bricked(c["stored"], c["dims"], c["cam"], c["tf"], 0.5, 0.99, pixels=pix)
+    return int(res.samples.sum()), time.perf_counter() - t0
+
+
+def cpu_baseline(vol, recipe, brick, view, rgba, vmin, vmax, seconds, workers):
+    from oracle import raycast as rc
+    dims = recipe.dims
+    _CPU.update(stored=rc.store_bricks(vol, rc.brick_grid(dims, (brick,) * 3)), dims=dims,
+                cam=rc.Camera(view.modelview, view.projection, view.width, view.height),
+                tf=rc.TransferFunction(rgba, vmin, vmax))
+    rng = np.random.default_rng(20240601)
+    # calibration on a few pixels (not counted)
+    cal = np.stack([rng.integers(0, view.width, 48), rng.integers(0, view.height, 48)], axis=1)
+    _, tc = _cpu_chunk(cal)
+    per_px = tc / len(cal)
+    n_px = max(workers * 16, int(seconds * workers / max(per_px, 1e-6)))
+    pix = np.stack([rng.integers(0, view.width, n_px), rng.integers(0, view.height, n_px)], axis=1)
+    chunks = np.array_split(pix, workers * 4)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        out = pool.map(_cpu_chunk, chunks)
+    wall = time.perf_counter() - t0
+    samples = sum(o[0] for o in out)
+    _CPU.clear()
+    return {"value": samples / wall / 1e9, "unit": "Gsamples/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n_px} uniformly drawn pixels of orbit frame 0 (seeded), FP64 bricked oracle with "
+                      f"near-tie branches, {samples} samples in {wall:.1f} s over {workers} forked processes"}
+
+
+# ------------------------------------------------------------------ GPU
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; --gpus must be 1 (no multi-GPU path is built)",
+              file=sys.stderr)
+        sys.exit(2)
+    recipe, brick, W, H = WORKLOADS[args.workload]
+    t = time.perf_counter()
+    vol = synth.make_cube(recipe, workers=min(16, os.cpu_count() or 1))
+    vmin, vmax = float(vol.min()), float(vol.max())
+    log(f"cube {recipe.dims} generated in {time.perf_counter() - t:.1f} s; range [{vmin:.3f}, {vmax:.3f}]")
+    rgba = synth.ramp_tf(vmin, vmax)
+    views = views_for(recipe, W, H)
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(vol, recipe, brick, views[0], rgba, vmin, vmax, args.cpu_seconds, workers)
+        log(f"cpu baseline: {cpu['value'] * 1e3:.4f} Msamples/s on {cpu['cores']} processes")
+
+    import torch
+    from paper_1205_0282_amd import binding
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    bc = binding.BrickCaster(0)
+    bc.plan(recipe.dims, (brick,) * 3, storage=args.storage, src_dtype="f32", max_views=1, max_w=W, max_h=H)
+    bc.bind()
+    t = time.perf_counter()
+    src = torch.from_numpy(vol).to(dev)
+    bc.load(src)
+    torch.cuda.synchronize()
+    del src
+    del vol
+    torch.cuda.empty_cache()
+    log(f"bricks loaded in {time.perf_counter() - t:.1f} s")
+    bc.set_transfer_function(rgba, vmin, vmax)
+    out = torch.empty((1, H, W, 4), dtype=torch.float32, device=dev)
+
+    # per orbit frame: samples and algorithmic bytes of the ray-casting launch (untimed)
+    lohi, _, _ = bc.bricks()
+    ebytes = {"f32": 4, "f16": 2, "fp8": 1}[args.storage]
+    core_bytes = np.prod((lohi[:, 3:] - lohi[:, :3]).astype(np.int64), axis=1) * ebytes
+    samples, algo_bytes, tiles = [], [], []
+    for v in views:
+        bc.set_views([v])
+        bc.render(out)
+        st = bc.stats()
+        r = bc.rects(0)
+        live = (r[:, 2] > r[:, 0]) & (r[:, 3] > r[:, 1])
+        samples.append(st["nominal_samples"])
+        tiles.append(st["n_tiles"])
+        algo_bytes.append(int(core_bytes[live].sum()) + st["n_tiles"] * 64 * 16)
+    log(f"orbit: mean {np.mean(samples) / 1e6:.1f} M samples/frame, {np.mean(tiles):.0f} tiles/frame")
+
+    for i in range(args.warmup):
+        bc.set_views([views[i % ORBIT]])
+        bc.render(out)
+    torch.cuda.synchronize()
+    bc.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        bc.set_views([views[i % ORBIT]])
+        bc.render(out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_ms, n_timed = bc.timing()
+    bc.enable_timing(False)
+    assert n_timed == args.steps, (n_timed, args.steps)
+
+    idx = [i % ORBIT for i in range(args.steps)]
+    tot_samples = float(sum(samples[i] for i in idx))
+    tot_bytes = float(sum(algo_bytes[i] for i in idx))
+    render_s = stage_ms[1] / 1e3
+    achieved = tot_bytes / render_s / 1e9
+    ms_step = elapsed / args.steps * 1e3
+    result = {
+        "metric": "Gsamples/s + fps @1920x1080 on 1024^3 cube",
+        "value": tot_samples / elapsed / 1e9,
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "fps": 1e3 / ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16 storage, f32 arithmetic",
+                  "fp8": "fp8-e4m3 storage, f32 arithmetic"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cube": list(recipe.dims), "brick": brick,
+                   "image": [W, H], "step_vox": 0.5, "ert": 0.99, "storage": args.storage,
+                   "orbit_frames": ORBIT, "views_per_launch": 1},
+        "stage_ms_per_frame": {"setup": stage_ms[0] / n_timed, "render": stage_ms[1] / n_timed,
+                               "composite": stage_ms[2] / n_timed},
+        "samples_per_frame": tot_samples / args.steps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "render_kernel", "algo_bytes_per_launch": tot_bytes / args.steps},
+        "cpu_baseline": cpu,
+    }
+    bc.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

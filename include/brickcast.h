@@ -88,8 +88,8 @@ typedef struct {
  *   bytes_out[1] metadata       (brick table, views, order, rectangles, queue, counters, table)
  *   bytes_out[2] sub-images     (max_tiles sub-image tiles of 8x8 RGBA float32)
  *   bytes_out[3] load scratch   (one brick's source region, used when the source is on the host)
- * max_tiles = 0 picks a default bound (views * screen tiles * (bricks along the
- * three axes)).  Every region is 256-byte aligned by the caller.
+ * max_tiles = 0 picks a default bound: views * screen tiles * min(bricks,
+ * 2 * (bricks along x + along y + along z) + 4).  Every region is 256-byte aligned by the caller.
  * Errors: BC_E_ARG for null pointers, non-positive dims, a share outside the
  * cube, ghost != 1, unknown storage/src_dtype, max_views not in [1, 4],
  * max_w/max_h not in [1, 16384], more than 4096 bricks. */
@@ -155,6 +155,19 @@ typedef struct {
   uint32_t reserved;
 } bc_frame_stats;
 int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);
+
+/* Per-stage GPU time, measured with HIP events recorded on the frame's own
+ * stream.  bc_enable_timing(ctx, 1) waits for the last frame and opens a new
+ * measurement window; each following bc_render_frame (at most 4096 of them)
+ * records an event before the set-up kernel, before the ray-casting kernel,
+ * before the compositing kernel and after it.  bc_enable_timing(ctx, 0) stops
+ * recording.  bc_get_timing waits for the last frame and writes the summed
+ * milliseconds of the window's frames per stage: ms_out[0] set-up, ms_out[1]
+ * ray casting, ms_out[2] compositing; *n_frames (may be NULL) receives the
+ * number of frames summed.  Errors: BC_E_STATE on a host-only context,
+ * BC_E_ARG for a null ms_out. */
+int bc_enable_timing(bc_ctx* ctx, int enable);
+int bc_get_timing(bc_ctx* ctx, double ms_out[3], int* n_frames);
 
 /* Brick table after bc_load_bricks: per brick the core box lo/hi (6 int32,
  * global voxel coordinates) and the FP8 (scale, offset) (1, 0 otherwise),

@@ -23,6 +23,7 @@ EXPORTS = [
     "bc_create", "bc_destroy", "bc_last_error", "bc_plan", "bc_bind_memory", "bc_load_bricks",
     "bc_set_transfer_function", "bc_set_view", "bc_render_frame", "bc_get_frame_stats",
     "bc_get_bricks", "bc_get_visibility_order", "bc_get_rects", "bc_read_brick",
+    "bc_enable_timing", "bc_get_timing",
 ]
 
 
@@ -78,6 +79,8 @@ def load_library(path: str = LIB_PATH):
         "bc_get_visibility_order": (I, [P, I, C.POINTER(C.c_int32), I]),
         "bc_get_rects": (I, [P, I, C.POINTER(C.c_int32), I]),
         "bc_read_brick": (I, [P, I, P, C.c_size_t, C.POINTER(C.c_int32)]),
+        "bc_enable_timing": (I, [P, I]),
+        "bc_get_timing": (I, [P, C.POINTER(C.c_double), C.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -204,6 +207,17 @@ class BrickCaster:
         self._check(self.lib.bc_get_frame_stats(self.h, C.byref(s)))
         return {"nominal_samples": int(s.nominal_samples), "evaluated_samples": int(s.evaluated_samples),
                 "n_tiles": int(s.n_tiles)}
+
+    def enable_timing(self, on=True):
+        self._check(self.lib.bc_enable_timing(self.h, 1 if on else 0))
+
+    def timing(self):
+        """(summed ms of set-up, ray casting, compositing; frames) since
+        enable_timing."""
+        ms = (C.c_double * 3)()
+        n = C.c_int()
+        self._check(self.lib.bc_get_timing(self.h, ms, C.byref(n)))
+        return [float(x) for x in ms], int(n.value)
 
     def bricks(self):
         n = C.c_int()

@@ -22,6 +22,8 @@ thread_local std::string g_create_error;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr int kMaxTimedFrames = 4096;
+
 }  // namespace
 
 struct bc_ctx {
@@ -59,6 +61,11 @@ struct bc_ctx {
   std::vector<bc_view> views;
   // kernel launch shape
   int render_workgroups = 0;
+  // per-stage timing: 4 events per frame (before setup, before render, before
+  // composite, after composite) recorded on the frame's stream
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  int timed_frames = 0;
 };
 
 namespace {
@@ -255,6 +262,7 @@ void bc_destroy(bc_ctx* c) {
       if (c->pinned[i]) (void)hipHostFree(c->pinned[i]);
     }
     if (c->frame_done) (void)hipEventDestroy(c->frame_done);
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     if (c->load_staging) (void)hipHostFree(c->load_staging);
   }
   delete c;
@@ -273,8 +281,8 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
     if (d->share_lo[a] < 0 || d->share_hi[a] > d->global_dims[a] || d->share_lo[a] >= d->share_hi[a])
       return fail(c, BC_E_ARG, "bc_plan: share [%lld, %lld) on axis %d is empty or outside the cube",
                   (long long)d->share_lo[a], (long long)d->share_hi[a], a);
-    if (d->brick_dims[a] < 4 || d->brick_dims[a] > 1024)
-      return fail(c, BC_E_ARG, "bc_plan: brick_dims[%d] = %d outside [4, 1024]", a, d->brick_dims[a]);
+    if (d->brick_dims[a] < 1 || d->brick_dims[a] > 1024)
+      return fail(c, BC_E_ARG, "bc_plan: brick_dims[%d] = %d outside [1, 1024]", a, d->brick_dims[a]);
   }
   if (d->ghost != 1) return fail(c, BC_E_ARG, "bc_plan: ghost must be 1");
   if (d->storage < 0 || d->storage > 2) return fail(c, BC_E_ARG, "bc_plan: unknown storage %d", d->storage);
@@ -325,7 +333,7 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
       }
   const int64_t tiles_frame = (int64_t)((max_w + BC_TILE - 1) / BC_TILE) * ((max_h + BC_TILE - 1) / BC_TILE);
   if (max_tiles == 0)
-    max_tiles = (int64_t)max_views * tiles_frame * std::min<int64_t>(nbt, (int64_t)nb[0] + nb[1] + nb[2] + 1);
+    max_tiles = (int64_t)max_views * tiles_frame * std::min<int64_t>(nbt, 2 * ((int64_t)nb[0] + nb[1] + nb[2]) + 4);
   c->max_tiles = max_tiles;
   c->bytes[0] = align256((size_t)off * c->elem_bytes);
   size_t m = 0;
@@ -548,9 +556,24 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
   c->copy_pending[slot] = true;
   c->frame_views = n;
   BcFramePtrs f = frame_ptrs(c);
+  hipEvent_t* ev = nullptr;
+  if (c->timing && c->timed_frames < kMaxTimedFrames) {
+    const size_t need = 4 * (size_t)(c->timed_frames + 1);
+    while (c->tev.size() < need) {
+      hipEvent_t e;
+      HIPCHECK(c, hipEventCreate(&e));
+      c->tev.push_back(e);
+    }
+    ev = &c->tev[4 * (size_t)c->timed_frames];
+    ++c->timed_frames;
+  }
+  if (ev) HIPCHECK(c, hipEventRecord(ev[0], st));
   HIPCHECK(c, bc_launch_setup(f, st));
+  if (ev) HIPCHECK(c, hipEventRecord(ev[1], st));
   HIPCHECK(c, bc_launch_render(f, c->render_workgroups, st));
+  if (ev) HIPCHECK(c, hipEventRecord(ev[2], st));
   HIPCHECK(c, bc_launch_composite(f, reinterpret_cast<float4*>(out), st));
+  if (ev) HIPCHECK(c, hipEventRecord(ev[3], st));
   HIPCHECK(c, hipEventRecord(c->frame_done, st));
   c->frame_pending = true;
   return BC_OK;
@@ -571,6 +594,40 @@ int bc_get_frame_stats(bc_ctx* c, bc_frame_stats* s) {
   s->evaluated_samples = h.evaluated;
   s->n_tiles = h.n_items;
   s->reserved = 0;
+  return BC_OK;
+}
+
+int bc_enable_timing(bc_ctx* c, int enable) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (c->device < 0) return fail(c, BC_E_STATE, "bc_enable_timing: host-only context");
+  HIPCHECK(c, hipSetDevice(c->device));
+  int r = wait_frame(c);
+  if (r) return r;
+  c->timing = enable != 0;
+  c->timed_frames = 0;
+  return BC_OK;
+}
+
+int bc_get_timing(bc_ctx* c, double ms_out[3], int* n_frames) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!ms_out) return fail(c, BC_E_ARG, "bc_get_timing: ms_out is NULL");
+  if (c->device < 0) return fail(c, BC_E_STATE, "bc_get_timing: host-only context");
+  HIPCHECK(c, hipSetDevice(c->device));
+  int r = wait_frame(c);
+  if (r) return r;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < c->timed_frames; ++k) {
+    const hipEvent_t* ev = &c->tev[4 * (size_t)k];
+    for (int s = 0; s < 3; ++s) {
+      float ms = 0.0f;
+      HIPCHECK(c, hipEventElapsedTime(&ms, ev[s], ev[s + 1]));
+      acc[s] += ms;
+    }
+  }
+  for (int s = 0; s < 3; ++s) ms_out[s] = acc[s];
+  if (n_frames) *n_frames = c->timed_frames;
   return BC_OK;
 }
 

@@ -77,7 +77,7 @@ def test_plan_sizes(lib, host_ctx):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("global_dims", (0, 64, 64)), ("brick_dims", (2, 32, 32)), ("ghost", 2), ("storage", 7),
+    ("global_dims", (0, 64, 64)), ("brick_dims", (0, 32, 32)), ("ghost", 2), ("storage", 7),
     ("src_dtype", 2), ("share_hi", (65, 64, 64)), ("share_lo", (10, 0, 0))])
 def test_plan_rejects_bad_desc(lib, host_ctx, field, value):
     d = _desc()
