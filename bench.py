@@ -157,7 +157,7 @@ def main():
     lohi, _, _ = bc.bricks()
     ebytes = {"f32": 4, "f16": 2, "fp8": 1}[args.storage]
     core_bytes = np.prod((lohi[:, 3:] - lohi[:, :3]).astype(np.int64), axis=1) * ebytes
-    samples, algo_bytes, tiles = [], [], []
+    samples, evaluated, algo_bytes, tiles = [], [], [], []
     for v in views:
         bc.set_views([v])
         bc.render(out)
@@ -165,6 +165,7 @@ def main():
         r = bc.rects(0)
         live = (r[:, 2] > r[:, 0]) & (r[:, 3] > r[:, 1])
         samples.append(st["nominal_samples"])
+        evaluated.append(st["evaluated_samples"])
         tiles.append(st["n_tiles"])
         algo_bytes.append(int(core_bytes[live].sum()) + st["n_tiles"] * 64 * 16)
     log(f"orbit: mean {np.mean(samples) / 1e6:.1f} M samples/frame, {np.mean(tiles):.0f} tiles/frame")
@@ -212,6 +213,7 @@ def main():
         "stage_ms_per_frame": {"setup": stage_ms[0] / n_timed, "render": stage_ms[1] / n_timed,
                                "composite": stage_ms[2] / n_timed},
         "samples_per_frame": tot_samples / args.steps,
+        "evaluated_per_frame": float(sum(evaluated[i] for i in idx)) / args.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "render_kernel", "algo_bytes_per_launch": tot_bytes / args.steps},

@@ -85,7 +85,8 @@ typedef struct {
 /* Sizes (bytes) of the four device regions for a volume and the largest frame
  * to be rendered:
  *   bytes_out[0] brick pool     (bricks with ghosts, Z-order micro-blocks)
- *   bytes_out[1] metadata       (brick table, views, order, rectangles, queue, counters, table)
+ *   bytes_out[1] metadata       (brick table, views, order, rectangles, queue, counters, table,
+ *                                one occupancy bit per interpolation cell of every brick)
  *   bytes_out[2] sub-images     (max_tiles sub-image tiles of 8x8 RGBA float32)
  *   bytes_out[3] load scratch   (one brick's source region, used when the source is on the host)
  * max_tiles = 0 picks a default bound: views * screen tiles * min(bricks,
@@ -156,6 +157,18 @@ typedef struct {
 } bc_frame_stats;
 int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);
 
+/* Options (any time after bc_create; they apply from the next frame).
+ *  BC_OPT_EMPTY_SKIP (default 1): samples whose interpolation cell cannot reach
+ *    a transfer-function entry of non-zero opacity add exactly nothing to their
+ *    ray; with 1 they are counted but not evaluated (the image is bit-identical
+ *    to 0).  The per-cell classification is recomputed on the device whenever
+ *    the opacity-corrected table changes.
+ *  BC_OPT_RENDER_WORKGROUPS: workgroups (256 threads) of the persistent
+ *    ray-casting launch; default 8 per compute unit.
+ * Errors: BC_E_ARG for an unknown option or a value out of range. */
+enum bc_option { BC_OPT_EMPTY_SKIP = 0, BC_OPT_RENDER_WORKGROUPS = 1 };
+int bc_set_option(bc_ctx* ctx, int option, int64_t value);
+
 /* Per-stage GPU time, measured with HIP events recorded on the frame's own
  * stream.  bc_enable_timing(ctx, 1) waits for the last frame and opens a new
  * measurement window; each following bc_render_frame (at most 4096 of them)
@@ -183,9 +196,49 @@ int bc_get_rects(bc_ctx* ctx, int view, int32_t* rects, int cap);
 
 /* Copy the stored elements of brick `b` (ghosted, padded to a multiple of 4
  * per axis, 4x4x4 micro-blocks in row-major order, voxels inside a
- * micro-block in Morton order) to host memory `dst` of `cap` bytes, and report
+ * micro-block x fastest) to host memory `dst` of `cap` bytes, and report
  * the padded dims.  For tests of the layout and the encoders. */
 int bc_read_brick(bc_ctx* ctx, int b, void* dst, size_t cap, int32_t padded_dims[3]);
+
+/* ---------------------------------------------------------------------------
+ * Learned upsampler (no passage in the paper: an addition that reconstructs a
+ * full-resolution, fine-step frame from a half-resolution, coarse-step one).
+ * Network: three 3x3 convolutions with zero padding, 4 -> 32 (ReLU) -> 32
+ * (ReLU) -> 16, then a 2x2 pixel shuffle (channel 4c + 2dy + dx goes to fine
+ * pixel (2i+dy, 2j+dx), channel c) plus the bilinear 2x upsampling of the input
+ * (half-pixel centres, clamped).  BF16 operands, FP32 accumulation, FP32
+ * master weights.  Parameters: CNN_N_PARAMS = 15056 floats, in the order
+ * W1[32][4][3][3] b1[32] W2[32][32][3][3] b2[32] W3[16][32][3][3] b3[16].
+ * Images are NHWC float32 RGBA device buffers, 16-byte aligned: coarse
+ * n x h x w x 4, fine n x 2h x 2w x 4.
+ *
+ * bc_cnn_plan: workspace bytes for up to max_n images of max_h x max_w coarse
+ *   pixels (parameters, Adam moments, packed BF16 weights, activations,
+ *   per-tile partial sums).  BC_E_ARG outside 1 <= max_n <= 64, sizes in
+ *   [1, 8192]; BC_E_STATE once bound.
+ * bc_cnn_bind: caller-allocated device workspace (256-byte aligned), kept alive
+ *   by the caller; BC_E_NOMEM if smaller than planned.
+ * bc_cnn_set_weights: copy n = 15056 host floats (and optionally both Adam
+ *   moments, else zeros) and the Adam step count; all finite.  For a
+ *   checkpoint, bc_cnn_get_weights returns the same four items.
+ * bc_cnn_forward: enqueue inference of n coarse images on `stream`.
+ * bc_cnn_gradients: gradient of the mean squared error over all fine pixels
+ *   and channels with respect to the parameters, into host `grad` (may be NULL),
+ *   and the loss into host `loss` (may be NULL); synchronous; no update.
+ * bc_cnn_train_step: gradient as above, then one bias-corrected Adam step
+ *   (beta 0.9 / 0.999, eps 1e-8, learning rate lr > 0) on `stream`; if `loss` is
+ *   non-NULL the call waits and returns the loss before the update.
+ * Errors: BC_E_STATE before bind / weights, BC_E_ARG for null or misaligned
+ * images, sizes beyond the plan, n != 15056, non-finite values. */
+int bc_cnn_plan(bc_ctx* ctx, int max_n, int max_h, int max_w, size_t* bytes);
+int bc_cnn_bind(bc_ctx* ctx, void* workspace, size_t bytes);
+int bc_cnn_set_weights(bc_ctx* ctx, const float* w, const float* adam_m, const float* adam_v, size_t n, int64_t step);
+int bc_cnn_get_weights(bc_ctx* ctx, float* w, float* adam_m, float* adam_v, size_t n, int64_t* step);
+int bc_cnn_forward(bc_ctx* ctx, const float* coarse, float* fine, int n, int h, int w, void* stream);
+int bc_cnn_gradients(bc_ctx* ctx, const float* coarse, const float* target, int n, int h, int w, float* grad,
+                     float* loss);
+int bc_cnn_train_step(bc_ctx* ctx, const float* coarse, const float* target, int n, int h, int w, float lr,
+                      float* loss, void* stream);
 
 #ifdef __cplusplus
 }

@@ -23,8 +23,12 @@ EXPORTS = [
     "bc_create", "bc_destroy", "bc_last_error", "bc_plan", "bc_bind_memory", "bc_load_bricks",
     "bc_set_transfer_function", "bc_set_view", "bc_render_frame", "bc_get_frame_stats",
     "bc_get_bricks", "bc_get_visibility_order", "bc_get_rects", "bc_read_brick",
-    "bc_enable_timing", "bc_get_timing",
+    "bc_enable_timing", "bc_get_timing", "bc_set_option",
+    "bc_cnn_plan", "bc_cnn_bind", "bc_cnn_set_weights", "bc_cnn_get_weights", "bc_cnn_forward",
+    "bc_cnn_gradients", "bc_cnn_train_step",
 ]
+CNN_N_PARAMS = 15056
+BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS = 0, 1
 
 
 class LibraryMissing(RuntimeError):
@@ -80,6 +84,14 @@ def load_library(path: str = LIB_PATH):
         "bc_get_rects": (I, [P, I, C.POINTER(C.c_int32), I]),
         "bc_read_brick": (I, [P, I, P, C.c_size_t, C.POINTER(C.c_int32)]),
         "bc_enable_timing": (I, [P, I]),
+        "bc_set_option": (I, [P, I, I64]),
+        "bc_cnn_plan": (I, [P, I, I, I, C.POINTER(C.c_size_t)]),
+        "bc_cnn_bind": (I, [P, P, C.c_size_t]),
+        "bc_cnn_set_weights": (I, [P, C.POINTER(F), C.POINTER(F), C.POINTER(F), C.c_size_t, I64]),
+        "bc_cnn_get_weights": (I, [P, C.POINTER(F), C.POINTER(F), C.POINTER(F), C.c_size_t, C.POINTER(I64)]),
+        "bc_cnn_forward": (I, [P, P, P, I, I, I, P]),
+        "bc_cnn_gradients": (I, [P, P, P, I, I, I, C.POINTER(F), C.POINTER(F)]),
+        "bc_cnn_train_step": (I, [P, P, P, I, I, I, F, C.POINTER(F), P]),
         "bc_get_timing": (I, [P, C.POINTER(C.c_double), C.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
@@ -208,6 +220,9 @@ class BrickCaster:
         return {"nominal_samples": int(s.nominal_samples), "evaluated_samples": int(s.evaluated_samples),
                 "n_tiles": int(s.n_tiles)}
 
+    def set_option(self, option, value):
+        self._check(self.lib.bc_set_option(self.h, int(option), int(value)))
+
     def enable_timing(self, on=True):
         self._check(self.lib.bc_enable_timing(self.h, 1 if on else 0))
 
@@ -218,6 +233,61 @@ class BrickCaster:
         n = C.c_int()
         self._check(self.lib.bc_get_timing(self.h, ms, C.byref(n)))
         return [float(x) for x in ms], int(n.value)
+
+    # -------------------------------------------------------- upsampler
+    def cnn_setup(self, max_n, max_h, max_w):
+        import torch
+        nb = C.c_size_t()
+        self._check(self.lib.bc_cnn_plan(self.h, max_n, max_h, max_w, C.byref(nb)))
+        self.cnn_ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=torch.device("cuda", self.device))
+        self._check(self.lib.bc_cnn_bind(self.h, C.c_void_p(self.cnn_ws.data_ptr()), self.cnn_ws.numel()))
+
+    def cnn_set_weights(self, w, adam_m=None, adam_v=None, step=0):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        m = None if adam_m is None else np.ascontiguousarray(adam_m, dtype=np.float32)
+        v = None if adam_v is None else np.ascontiguousarray(adam_v, dtype=np.float32)
+        self._check(self.lib.bc_cnn_set_weights(self.h, _ptr(w, C.c_float), None if m is None else _ptr(m, C.c_float),
+                                                None if v is None else _ptr(v, C.c_float), w.size, int(step)))
+
+    def cnn_get_weights(self):
+        w = np.zeros(CNN_N_PARAMS, np.float32)
+        m = np.zeros(CNN_N_PARAMS, np.float32)
+        v = np.zeros(CNN_N_PARAMS, np.float32)
+        step = C.c_int64()
+        self._check(self.lib.bc_cnn_get_weights(self.h, _ptr(w, C.c_float), _ptr(m, C.c_float), _ptr(v, C.c_float),
+                                                CNN_N_PARAMS, C.byref(step)))
+        return w, m, v, int(step.value)
+
+    def cnn_forward(self, coarse, out=None, stream=None):
+        """coarse: (n, h, w, 4) float32 CUDA tensor -> (n, 2h, 2w, 4)."""
+        import torch
+        n, h, w, _ = coarse.shape
+        if out is None:
+            out = torch.empty((n, 2 * h, 2 * w, 4), dtype=torch.float32, device=coarse.device)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self.lib.bc_cnn_forward(self.h, C.c_void_p(coarse.data_ptr()), C.c_void_p(out.data_ptr()),
+                                            n, h, w, C.c_void_p(st)))
+        return out
+
+    def cnn_gradients(self, coarse, target):
+        import torch
+        torch.cuda.synchronize()
+        n, h, w, _ = coarse.shape
+        g = np.zeros(CNN_N_PARAMS, np.float32)
+        loss = C.c_float()
+        self._check(self.lib.bc_cnn_gradients(self.h, C.c_void_p(coarse.data_ptr()), C.c_void_p(target.data_ptr()),
+                                              n, h, w, _ptr(g, C.c_float), C.byref(loss)))
+        return g, float(loss.value)
+
+    def cnn_train_step(self, coarse, target, lr=1e-3, want_loss=True, stream=None):
+        import torch
+        n, h, w, _ = coarse.shape
+        loss = C.c_float()
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self.lib.bc_cnn_train_step(self.h, C.c_void_p(coarse.data_ptr()), C.c_void_p(target.data_ptr()),
+                                               n, h, w, float(lr), C.byref(loss) if want_loss else None,
+                                               C.c_void_p(st)))
+        return float(loss.value) if want_loss else None
 
     def bricks(self):
         n = C.c_int()
@@ -252,15 +322,15 @@ class BrickCaster:
 
 
 def unswizzle(buf, padded_dims):
-    """Stored brick elements (4x4x4 micro-blocks, Morton inside) -> array [z][y][x]
+    """Stored brick elements (4x4x4 micro-blocks, x fastest inside) -> array [z][y][x]
     of the padded ghosted brick.  For layout tests."""
     gx, gy, gz = padded_dims
     mbx, mby, mbz = gx // 4, gy // 4, gz // 4
     e = np.arange(gx * gy * gz)
     mbi, inn = e >> 6, e & 63
-    wx = (inn & 1) | ((inn >> 2) & 2)
-    wy = ((inn >> 1) & 1) | ((inn >> 3) & 2)
-    wz = ((inn >> 2) & 1) | ((inn >> 4) & 2)
+    wx = inn & 3
+    wy = (inn >> 2) & 3
+    wz = inn >> 4
     x = (mbi % mbx) * 4 + wx
     y = ((mbi // mbx) % mby) * 4 + wy
     z = (mbi // (mbx * mby)) * 4 + wz

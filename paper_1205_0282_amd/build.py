@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbrickcast.so")
-SOURCES = ["bc_api.cpp", "bc_load.hip", "bc_frame.hip"]
+SOURCES = ["bc_api.cpp", "bc_load.hip", "bc_frame.hip", "bc_render.hip", "bc_cnn.hip"]
 ARCH = os.environ.get("BC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/brickcast.h"
+#include "bc_cnn.h"
 #include "bc_kernels.h"
 #include "bc_types.h"
 
@@ -41,7 +42,8 @@ struct bc_ctx {
   size_t elem_bytes = 4, src_elem_bytes = 4;
   size_t bytes[4] = {0, 0, 0, 0};
   size_t off_bricks = 0, off_fin = 0, off_views = 0, off_order = 0, off_rects = 0, off_item_base = 0,
-         off_ctr = 0;
+         off_ctr = 0, off_occ = 0;
+  int max_occ_words = 0;
   void* dev[4] = {nullptr, nullptr, nullptr, nullptr};
   // per-frame input ring (pinned host memory) and events
   BcFrameIn* pinned[2] = {nullptr, nullptr};
@@ -59,8 +61,19 @@ struct bc_ctx {
   int K = 0;
   double vmin = 0, vmax = 1, dt_ref = 1;
   std::vector<bc_view> views;
-  // kernel launch shape
+  // kernel launch shape and options
   int render_workgroups = 0;
+  bool ess = true;
+  // cell-occupancy bits are valid for this table (opacity-corrected entries)
+  bool occ_valid = false;
+  std::vector<float> occ_table;
+  // learned upsampler: caller-bound workspace (see cnn_layout)
+  bool cnn_planned = false, cnn_bound = false, cnn_has_w = false;
+  int cnn_max_n = 0, cnn_max_h = 0, cnn_max_w = 0;
+  size_t cnn_bytes = 0;
+  char* cnn_ws = nullptr;
+  int64_t cnn_step = 0;
+  std::vector<float> cnn_loss_host;
   // per-stage timing: 4 events per frame (before setup, before render, before
   // composite, after composite) recorded on the frame's stream
   bool timing = false;
@@ -192,6 +205,9 @@ BcFramePtrs frame_ptrs(bc_ctx* c) {
   f.ctr = reinterpret_cast<BcCounters*>(meta + c->off_ctr);
   f.sub = static_cast<float4*>(c->dev[2]);
   f.pool = c->dev[0];
+  f.occ = reinterpret_cast<uint32_t*>(meta + c->off_occ);
+  f.ess = c->ess ? 1 : 0;
+  f.K = c->K;
   f.n_bricks = c->n_bricks;
   f.n_views = c->frame_views;
   for (int a = 0; a < 3; ++a) f.gdims[a] = (int32_t)c->desc.global_dims[a];
@@ -310,7 +326,7 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
   c->elem_bytes = d->storage == BC_F32 ? 4 : (d->storage == BC_F16 ? 2 : 1);
   c->src_elem_bytes = d->src_dtype == BC_F32 ? 4 : 2;
   c->bricks.assign(c->n_bricks, BcBrick{});
-  int64_t off = 0;
+  int64_t off = 0, occ_words = 0, max_words = 0;
   size_t max_region = 0;
   for (int bz = 0; bz < nb[2]; ++bz)
     for (int by = 0; by < nb[1]; ++by)
@@ -329,6 +345,14 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
         b.scale = 1.0f;
         b.offs = 0.0f;
         off += (int64_t)b.gdim[0] * b.gdim[1] * b.gdim[2];
+        // interpolation cells per axis: core + 1 (between ghosted voxels i, i+1)
+        b.occ_w[0] = (b.hi[0] - b.lo[0] + 1 + 3) / 4;
+        b.occ_w[1] = (b.hi[1] - b.lo[1] + 1 + 3) / 4;
+        b.occ_w[2] = (b.hi[2] - b.lo[2] + 1 + 1) / 2;
+        b.occ_offset = occ_words;
+        const int64_t words = (int64_t)b.occ_w[0] * b.occ_w[1] * b.occ_w[2];
+        occ_words += words;
+        max_words = std::max<int64_t>(max_words, words);
         max_region = std::max(max_region, (size_t)region);
       }
   const int64_t tiles_frame = (int64_t)((max_w + BC_TILE - 1) / BC_TILE) * ((max_h + BC_TILE - 1) / BC_TILE);
@@ -344,12 +368,15 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
   c->off_rects = m; m = align256(m + sizeof(int32_t) * 4 * BC_MAX_VIEWS * c->n_bricks);
   c->off_item_base = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
   c->off_ctr = m; m = align256(m + sizeof(BcCounters));
+  c->off_occ = m; m = align256(m + sizeof(uint32_t) * (size_t)occ_words);
   c->bytes[1] = m;
+  c->max_occ_words = (int)max_words;
   c->bytes[2] = align256((size_t)max_tiles * BC_TILE * BC_TILE * 16);
   c->bytes[3] = align256(max_region * c->src_elem_bytes);
   for (int i = 0; i < 4; ++i) bytes_out[i] = c->bytes[i];
   c->planned = true;
   c->loaded = false;
+  c->occ_valid = false;
   return BC_OK;
 }
 
@@ -459,6 +486,7 @@ int bc_load_bricks(bc_ctx* c, const void* src, const int64_t strides[3], int src
   HIPCHECK(c, hipStreamSynchronize(st));
   HIPCHECK(c, hipMemcpy(c->bricks.data(), dbricks, sizeof(BcBrick) * c->n_bricks, hipMemcpyDeviceToHost));
   c->loaded = true;
+  c->occ_valid = false;
   return BC_OK;
 }
 
@@ -556,6 +584,18 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
   c->copy_pending[slot] = true;
   c->frame_views = n;
   BcFramePtrs f = frame_ptrs(c);
+  // empty-space classification depends on the corrected table only: redo it
+  // when the table differs from the one last classified
+  bool classify = false;
+  if (c->ess) {
+    const float* tab = &fin->table[0][0];
+    classify = !c->occ_valid || c->occ_table.size() != (size_t)(4 * c->K) ||
+               std::memcmp(c->occ_table.data(), tab, sizeof(float) * 4 * c->K) != 0;
+    if (classify) {
+      c->occ_table.assign(tab, tab + 4 * c->K);
+      c->occ_valid = true;
+    }
+  }
   hipEvent_t* ev = nullptr;
   if (c->timing && c->timed_frames < kMaxTimedFrames) {
     const size_t need = 4 * (size_t)(c->timed_frames + 1);
@@ -567,6 +607,7 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     ev = &c->tev[4 * (size_t)c->timed_frames];
     ++c->timed_frames;
   }
+  if (classify) HIPCHECK(c, bc_launch_classify(f, c->max_occ_words, st));
   if (ev) HIPCHECK(c, hipEventRecord(ev[0], st));
   HIPCHECK(c, bc_launch_setup(f, st));
   if (ev) HIPCHECK(c, hipEventRecord(ev[1], st));
@@ -595,6 +636,24 @@ int bc_get_frame_stats(bc_ctx* c, bc_frame_stats* s) {
   s->n_tiles = h.n_items;
   s->reserved = 0;
   return BC_OK;
+}
+
+int bc_set_option(bc_ctx* c, int option, int64_t value) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  switch (option) {
+    case BC_OPT_EMPTY_SKIP:
+      if (value != 0 && value != 1) return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_EMPTY_SKIP takes 0 or 1");
+      c->ess = value != 0;
+      return BC_OK;
+    case BC_OPT_RENDER_WORKGROUPS:
+      if (value < 1 || value > (1 << 20))
+        return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_RENDER_WORKGROUPS outside [1, 2^20]");
+      c->render_workgroups = (int)value;
+      return BC_OK;
+    default:
+      return fail(c, BC_E_ARG, "bc_set_option: unknown option %d", option);
+  }
 }
 
 int bc_enable_timing(bc_ctx* c, int enable) {
@@ -699,6 +758,274 @@ int bc_read_brick(bc_ctx* c, int b, void* dst, size_t cap, int32_t dims[3]) {
   HIPCHECK(c, hipSetDevice(c->device));
   (void)wait_frame(c);
   HIPCHECK(c, hipMemcpy(dst, static_cast<char*>(c->dev[0]) + br.offset * c->elem_bytes, bytes, hipMemcpyDeviceToHost));
+  return BC_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================
+// Learned upsampler
+// ======================================================================
+namespace {
+
+struct CnnLayout {
+  size_t w, m, v, g;                 // FP32 parameter vectors
+  size_t f1, f2, f3, b3, b2;         // packed fragments: forward 1..3, backward-data 3 and 2
+  size_t a1, a2, gy, gz2, gz1;       // BF16 NHWC activations / gradients
+  size_t part, loss;                 // per-tile partial sums
+  size_t total;
+  int64_t tiles;
+};
+
+// fragment bytes: ks * nt * 64 lanes * 8 BF16
+constexpr size_t frag_bytes(int ks, int nt) { return (size_t)ks * nt * 64 * 8 * 2; }
+constexpr int kPartWidth = 32 * 288 + 32;   // widest per-tile partial (layer 2)
+
+CnnLayout cnn_layout(int n, int h, int w) {
+  CnnLayout L;
+  size_t m = 0;
+  auto take = [&](size_t bytes) { size_t o = m; m = align256(m + bytes); return o; };
+  L.w = take(4 * CNN_N_PARAMS);
+  L.m = take(4 * CNN_N_PARAMS);
+  L.v = take(4 * CNN_N_PARAMS);
+  L.g = take(4 * CNN_N_PARAMS);
+  L.f1 = take(frag_bytes(2, 2));
+  L.f2 = take(frag_bytes(9, 2));
+  L.f3 = take(frag_bytes(9, 1));
+  L.b3 = take(frag_bytes(5, 2));
+  L.b2 = take(frag_bytes(9, 2));
+  const size_t px = (size_t)n * h * w;
+  L.a1 = take(px * 32 * 2);
+  L.a2 = take(px * 32 * 2);
+  L.gy = take(px * 16 * 2);
+  L.gz2 = take(px * 32 * 2);
+  L.gz1 = take(px * 32 * 2);
+  L.tiles = (int64_t)n * ((h + 15) / 16) * ((w + 15) / 16);
+  L.part = take((size_t)L.tiles * kPartWidth * 4);
+  L.loss = take((size_t)L.tiles * 4);
+  L.total = m;
+  return L;
+}
+
+CnnPackTable cnn_pack_table(bc_ctx* c, const CnnLayout& L) {
+  CnnPackTable t;
+  auto ent = [&](size_t off, int w_off, int cin, int cout, int ks, int nt, int tr) {
+    CnnPackEntry e;
+    e.dst = reinterpret_cast<uint16_t*>(c->cnn_ws + off);
+    e.w_off = w_off; e.cin = cin; e.cout = cout; e.ks = ks; e.nt = nt; e.transposed = tr;
+    return e;
+  };
+  t.e[0] = ent(L.f1, CNN_OFF_W1, 4, 32, 2, 2, 0);
+  t.e[1] = ent(L.f2, CNN_OFF_W2, 32, 32, 9, 2, 0);
+  t.e[2] = ent(L.f3, CNN_OFF_W3, 32, 16, 9, 1, 0);
+  t.e[3] = ent(L.b3, CNN_OFF_W3, 32, 16, 5, 2, 1);
+  t.e[4] = ent(L.b2, CNN_OFF_W2, 32, 32, 9, 2, 1);
+  t.n = 5;
+  return t;
+}
+
+int cnn_check_images(bc_ctx* c, const char* who, int n, int h, int w) {
+  if (!c->cnn_bound) return fail(c, BC_E_STATE, "%s: bind the upsampler workspace first", who);
+  if (!c->cnn_has_w) return fail(c, BC_E_STATE, "%s: set the upsampler weights first", who);
+  if (n < 1 || h < 1 || w < 1 || n > c->cnn_max_n || h > c->cnn_max_h || w > c->cnn_max_w)
+    return fail(c, BC_E_ARG, "%s: %d images of %d x %d exceed the planned %d of %d x %d", who, n, w, h, c->cnn_max_n,
+                c->cnn_max_w, c->cnn_max_h);
+  return BC_OK;
+}
+
+// forward + loss + backward into the gradient vector (no update)
+int cnn_gradients(bc_ctx* c, const float* coarse, const float* target, int n, int h, int w, hipStream_t st) {
+  const CnnLayout L = cnn_layout(n, h, w);
+  char* ws = c->cnn_ws;
+  auto U16 = [&](size_t off) { return reinterpret_cast<uint16_t*>(ws + off); };
+  auto F32 = [&](size_t off) { return reinterpret_cast<float*>(ws + off); };
+  auto FR = [&](size_t off) { return reinterpret_cast<const uint4*>(ws + off); };
+  const float* wts = F32(L.w);
+  CnnLayerArgs a{};
+  a.h = h; a.w = w;
+  // forward
+  a.img = coarse; a.in = nullptr; a.out = U16(L.a1); a.bias = wts + CNN_OFF_B1; a.wf = FR(L.f1);
+  HIPCHECK(c, cnn_launch_layer(1, 0, a, n, st));
+  a.img = nullptr; a.in = U16(L.a1); a.out = U16(L.a2); a.bias = wts + CNN_OFF_B2; a.wf = FR(L.f2);
+  HIPCHECK(c, cnn_launch_layer(2, 0, a, n, st));
+  a.img = coarse; a.in = U16(L.a2); a.out = U16(L.gy); a.bias = wts + CNN_OFF_B3; a.wf = FR(L.f3);
+  a.target = target; a.loss_part = F32(L.loss);
+  a.grad_scale = (float)(2.0 / ((double)n * 4.0 * h * w * 4.0));
+  HIPCHECK(c, cnn_launch_layer(3, 2, a, n, st));
+  // backward-data through layers 3 and 2 (ReLU masks from a2 and a1)
+  CnnLayerArgs bd{};
+  bd.h = h; bd.w = w;
+  bd.in = U16(L.gy); bd.out = U16(L.gz2); bd.mask = U16(L.a2); bd.wf = FR(L.b3);
+  HIPCHECK(c, cnn_launch_layer(3, 1, bd, n, st));
+  bd.in = U16(L.gz2); bd.out = U16(L.gz1); bd.mask = U16(L.a1); bd.wf = FR(L.b2);
+  HIPCHECK(c, cnn_launch_layer(2, 1, bd, n, st));
+  // backward-weights per layer, then deterministic reductions
+  float* g = F32(L.g);
+  struct { int layer, cin, cout; const float* img; const uint16_t* x; const uint16_t* gr; int w_off, b_off; } jobs[3] = {
+      {3, 32, 16, nullptr, U16(L.a2), U16(L.gy), CNN_OFF_W3, CNN_OFF_B3},
+      {2, 32, 32, nullptr, U16(L.a1), U16(L.gz2), CNN_OFF_W2, CNN_OFF_B2},
+      {1, 4, 32, coarse, nullptr, U16(L.gz1), CNN_OFF_W1, CNN_OFF_B1}};
+  for (auto& j : jobs) {
+    CnnWgradArgs wa{};
+    wa.img = j.img; wa.x = j.x; wa.g = j.gr; wa.part = F32(L.part); wa.h = h; wa.w = w;
+    HIPCHECK(c, cnn_launch_wgrad(j.layer, wa, n, st));
+    const int nw = j.cout * j.cin * 9;
+    HIPCHECK(c, cnn_launch_reduce(F32(L.part), L.tiles, nw + j.cout, g + j.w_off, g + j.b_off, nw, st));
+  }
+  return BC_OK;
+}
+
+int cnn_read_loss(bc_ctx* c, int n, int h, int w, float* loss, hipStream_t st) {
+  const CnnLayout L = cnn_layout(n, h, w);
+  c->cnn_loss_host.resize((size_t)L.tiles);
+  HIPCHECK(c, hipMemcpyAsync(c->cnn_loss_host.data(), c->cnn_ws + L.loss, sizeof(float) * L.tiles,
+                             hipMemcpyDeviceToHost, st));
+  HIPCHECK(c, hipStreamSynchronize(st));
+  double s = 0.0;
+  for (float v : c->cnn_loss_host) s += v;
+  *loss = (float)(s / ((double)n * 4.0 * h * w * 4.0));
+  return BC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bc_cnn_plan(bc_ctx* c, int max_n, int max_h, int max_w, size_t* bytes) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!bytes) return fail(c, BC_E_ARG, "bc_cnn_plan: bytes is NULL");
+  if (max_n < 1 || max_n > 64 || max_h < 1 || max_w < 1 || max_h > 8192 || max_w > 8192)
+    return fail(c, BC_E_ARG, "bc_cnn_plan: need 1 <= max_n <= 64 and coarse size in [1, 8192]");
+  if (c->cnn_bound) return fail(c, BC_E_STATE, "bc_cnn_plan: workspace already bound");
+  const CnnLayout L = cnn_layout(max_n, max_h, max_w);
+  c->cnn_max_n = max_n;
+  c->cnn_max_h = max_h;
+  c->cnn_max_w = max_w;
+  c->cnn_bytes = L.total;
+  c->cnn_planned = true;
+  *bytes = L.total;
+  return BC_OK;
+}
+
+int bc_cnn_bind(bc_ctx* c, void* ws, size_t bytes) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (c->device < 0) return fail(c, BC_E_STATE, "bc_cnn_bind: host-only context");
+  if (!c->cnn_planned) return fail(c, BC_E_STATE, "bc_cnn_bind: call bc_cnn_plan first");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return fail(c, BC_E_ARG, "bc_cnn_bind: workspace NULL or not 256-byte aligned");
+  if (bytes < c->cnn_bytes) return fail(c, BC_E_NOMEM, "bc_cnn_bind: %zu bytes, %zu planned", bytes, c->cnn_bytes);
+  c->cnn_ws = static_cast<char*>(ws);
+  c->cnn_bound = true;
+  c->cnn_has_w = false;
+  return BC_OK;
+}
+
+int bc_cnn_set_weights(bc_ctx* c, const float* w, const float* adam_m, const float* adam_v, size_t n, int64_t step) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!c->cnn_bound) return fail(c, BC_E_STATE, "bc_cnn_set_weights: bind the workspace first");
+  if (!w) return fail(c, BC_E_ARG, "bc_cnn_set_weights: w is NULL");
+  if (n != CNN_N_PARAMS) return fail(c, BC_E_ARG, "bc_cnn_set_weights: n = %zu, the network has %d parameters", n, CNN_N_PARAMS);
+  if ((adam_m == nullptr) != (adam_v == nullptr)) return fail(c, BC_E_ARG, "bc_cnn_set_weights: give both Adam moments or neither");
+  if (step < 0) return fail(c, BC_E_ARG, "bc_cnn_set_weights: step < 0");
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(w[i])) return fail(c, BC_E_ARG, "bc_cnn_set_weights: parameter %zu is not finite", i);
+  HIPCHECK(c, hipSetDevice(c->device));
+  (void)wait_frame(c);
+  const CnnLayout L = cnn_layout(c->cnn_max_n, c->cnn_max_h, c->cnn_max_w);
+  const size_t b = sizeof(float) * CNN_N_PARAMS;
+  HIPCHECK(c, hipMemcpy(c->cnn_ws + L.w, w, b, hipMemcpyHostToDevice));
+  if (adam_m) {
+    HIPCHECK(c, hipMemcpy(c->cnn_ws + L.m, adam_m, b, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->cnn_ws + L.v, adam_v, b, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> z(CNN_N_PARAMS, 0.0f);
+    HIPCHECK(c, hipMemcpy(c->cnn_ws + L.m, z.data(), b, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->cnn_ws + L.v, z.data(), b, hipMemcpyHostToDevice));
+  }
+  HIPCHECK(c, cnn_launch_pack(reinterpret_cast<const float*>(c->cnn_ws + L.w), cnn_pack_table(c, L), nullptr));
+  HIPCHECK(c, hipStreamSynchronize(nullptr));
+  c->cnn_step = step;
+  c->cnn_has_w = true;
+  return BC_OK;
+}
+
+int bc_cnn_get_weights(bc_ctx* c, float* w, float* adam_m, float* adam_v, size_t n, int64_t* step) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!c->cnn_has_w) return fail(c, BC_E_STATE, "bc_cnn_get_weights: no weights set");
+  if (n != CNN_N_PARAMS) return fail(c, BC_E_ARG, "bc_cnn_get_weights: n = %zu, the network has %d parameters", n, CNN_N_PARAMS);
+  HIPCHECK(c, hipSetDevice(c->device));
+  HIPCHECK(c, hipDeviceSynchronize());
+  const CnnLayout L = cnn_layout(c->cnn_max_n, c->cnn_max_h, c->cnn_max_w);
+  const size_t b = sizeof(float) * CNN_N_PARAMS;
+  if (w) HIPCHECK(c, hipMemcpy(w, c->cnn_ws + L.w, b, hipMemcpyDeviceToHost));
+  if (adam_m) HIPCHECK(c, hipMemcpy(adam_m, c->cnn_ws + L.m, b, hipMemcpyDeviceToHost));
+  if (adam_v) HIPCHECK(c, hipMemcpy(adam_v, c->cnn_ws + L.v, b, hipMemcpyDeviceToHost));
+  if (step) *step = c->cnn_step;
+  return BC_OK;
+}
+
+int bc_cnn_forward(bc_ctx* c, const float* coarse, float* fine, int n, int h, int w, void* stream) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!coarse || !fine) return fail(c, BC_E_ARG, "bc_cnn_forward: null image");
+  if ((reinterpret_cast<uintptr_t>(coarse) | reinterpret_cast<uintptr_t>(fine)) & 15)
+    return fail(c, BC_E_ARG, "bc_cnn_forward: images must be 16-byte aligned");
+  int r = cnn_check_images(c, "bc_cnn_forward", n, h, w);
+  if (r) return r;
+  HIPCHECK(c, hipSetDevice(c->device));
+  const CnnLayout L = cnn_layout(c->cnn_max_n, c->cnn_max_h, c->cnn_max_w);
+  CnnInferArgs a;
+  a.x = coarse; a.out = fine;
+  a.params = reinterpret_cast<const float*>(c->cnn_ws + L.w);
+  a.wf1 = reinterpret_cast<const uint4*>(c->cnn_ws + L.f1);
+  a.wf2 = reinterpret_cast<const uint4*>(c->cnn_ws + L.f2);
+  a.wf3 = reinterpret_cast<const uint4*>(c->cnn_ws + L.f3);
+  a.h = h; a.w = w;
+  HIPCHECK(c, cnn_launch_infer(a, n, static_cast<hipStream_t>(stream)));
+  return BC_OK;
+}
+
+int bc_cnn_gradients(bc_ctx* c, const float* coarse, const float* target, int n, int h, int w, float* grad,
+                     float* loss) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!coarse || !target) return fail(c, BC_E_ARG, "bc_cnn_gradients: null image");
+  int r = cnn_check_images(c, "bc_cnn_gradients", n, h, w);
+  if (r) return r;
+  HIPCHECK(c, hipSetDevice(c->device));
+  // the per-layer buffers are laid out for the size of this call
+  r = cnn_gradients(c, coarse, target, n, h, w, nullptr);
+  if (r) return r;
+  const CnnLayout L = cnn_layout(n, h, w);
+  if (grad) HIPCHECK(c, hipMemcpy(grad, c->cnn_ws + L.g, sizeof(float) * CNN_N_PARAMS, hipMemcpyDeviceToHost));
+  if (loss) return cnn_read_loss(c, n, h, w, loss, nullptr);
+  HIPCHECK(c, hipStreamSynchronize(nullptr));
+  return BC_OK;
+}
+
+int bc_cnn_train_step(bc_ctx* c, const float* coarse, const float* target, int n, int h, int w, float lr,
+                      float* loss, void* stream) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!coarse || !target) return fail(c, BC_E_ARG, "bc_cnn_train_step: null image");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(c, BC_E_ARG, "bc_cnn_train_step: lr must be finite and > 0");
+  int r = cnn_check_images(c, "bc_cnn_train_step", n, h, w);
+  if (r) return r;
+  HIPCHECK(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  r = cnn_gradients(c, coarse, target, n, h, w, st);
+  if (r) return r;
+  const CnnLayout Lg = cnn_layout(n, h, w);
+  const CnnLayout L = cnn_layout(c->cnn_max_n, c->cnn_max_h, c->cnn_max_w);
+  float* wv = reinterpret_cast<float*>(c->cnn_ws + L.w);
+  c->cnn_step += 1;
+  HIPCHECK(c, cnn_launch_adam(wv, reinterpret_cast<float*>(c->cnn_ws + L.m), reinterpret_cast<float*>(c->cnn_ws + L.v),
+                              reinterpret_cast<const float*>(c->cnn_ws + Lg.g), CNN_N_PARAMS, lr, c->cnn_step, st));
+  HIPCHECK(c, cnn_launch_pack(wv, cnn_pack_table(c, L), st));
+  if (loss) return cnn_read_loss(c, n, h, w, loss, st);
   return BC_OK;
 }
 

@@ -3,12 +3,6 @@
 //  setup     (FP64, one workgroup): inverse view transform, eye, per-brick
 //            visibility keys and their sort, per-brick rendering rectangles
 //            (Section 2.3.2, Figure 4) and the work-item prefix sums.
-//  render    persistent kernel: every wave pulls (brick, view, 8x8 tile) work
-//            items from a device counter and casts the tile's 64 rays through
-//            the brick: ray set-up, clipping to the cube and the brick, samples
-//            at a fixed step anchored at the cube entry, trilinear
-//            interpolation, transfer-function lookup, front-to-back
-//            compositing with early ray termination (Sections 1.2, 2.3.2).
 //  composite per pixel, folds the brick sub-images in visibility order with
 //            "over" (Section 2.3.3; associativity of alpha blending).
 #include <hip/hip_runtime.h>
@@ -16,7 +10,6 @@
 #include <float.h>
 #include "bc_types.h"
 #include "bc_kernels.h"
-#include "bc_df.h"
 
 namespace {
 
@@ -271,222 +264,6 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   }
 }
 
-// ------------------------------------------------------------------ rays
-__device__ __forceinline__ df dfv(float hi, float lo) { return df_make(hi, lo); }
-
-// smallest j >= 0 with t_in + (j + 1/2) dt >= t
-__device__ __forceinline__ int first_index(df t_in, df dt, df t) {
-  const df q = df_div(df_sub(t, t_in), dt);
-  float jf = ceilf(df_to_f(q) - 0.5f);
-  int j = (int)fmaxf(jf, 0.0f);
-  // exact fix-up against the sample-time formula
-  for (int it = 0; it < 3; ++it) {
-    const df tj = df_add(t_in, df_mul(df_from((float)j + 0.5f), dt));
-    if (df_lt(tj, t)) { ++j; continue; }
-    if (j > 0) {
-      const df tm = df_add(t_in, df_mul(df_from((float)j - 0.5f), dt));
-      if (df_ge(tm, t)) { --j; continue; }
-    }
-    break;
-  }
-  return j;
-}
-
-struct Slab { df t0, t1; bool miss; };
-
-__device__ __forceinline__ Slab slab_df(const df* o, const df* d, const float* lo, const float* hi) {
-  Slab s;
-  s.t0 = df_from(-INFINITY);
-  s.t1 = df_from(INFINITY);
-  s.miss = false;
-  for (int a = 0; a < 3; ++a) {
-    if (d[a].hi == 0.0f && d[a].lo == 0.0f) {
-      const float oa = df_to_f(o[a]);
-      const bool in = df_ge(o[a], df_from(lo[a])) && df_lt(o[a], df_from(hi[a]));
-      (void)oa;
-      if (!in) s.miss = true;
-      continue;
-    }
-    const df ta = df_div(df_sub(df_from(lo[a]), o[a]), d[a]);
-    const df tb = df_div(df_sub(df_from(hi[a]), o[a]), d[a]);
-    s.t0 = df_max(s.t0, df_min(ta, tb));
-    s.t1 = df_min(s.t1, df_max(ta, tb));
-  }
-  return s;
-}
-
-template <int FMT>
-__device__ __forceinline__ float fetch(const void* pool, int64_t idx, float s, float o) {
-  if (FMT == 0) return static_cast<const float*>(pool)[idx];
-  if (FMT == 1) return __half2float(static_cast<const __half*>(pool)[idx]);
-  const uint32_t c = static_cast<const uint8_t*>(pool)[idx];
-  const uint32_t e = (c >> 3) & 15u, m = c & 7u;
-  float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
-  mag = (c & 0x80u) ? -mag : mag;
-  return __builtin_fmaf(mag, s, o);
-}
-
-__device__ __forceinline__ int sx_(int r) { return (r & 1) | ((r & 2) << 2); }
-__device__ __forceinline__ int sy_(int r) { return ((r & 1) << 1) | ((r & 2) << 3); }
-__device__ __forceinline__ int sz_(int r) { return ((r & 1) << 2) | ((r & 2) << 4); }
-
-template <int FMT>
-__device__ void cast_ray(const BcFramePtrs& f, const BcViewParams& vp, const BcBrick& br,
-                         const float4* __restrict__ table, float tf_scale, float tf_bias, int K,
-                         int px, int py, float4& acc, uint32_t& nsamp) {
-  const int W = vp.width, H = vp.height;
-  const df x = df_div(df_from((float)(2 * px + 1 - W)), df_from((float)W));
-  const df y = df_div(df_from((float)(H - 2 * py - 1)), df_from((float)H));
-  df o[3], d[3];
-  if (vp.kind == 0) {
-    df u[3];
-    for (int a = 0; a < 3; ++a) {
-      o[a] = dfv(vp.e_hi[a], vp.e_lo[a]);
-      u[a] = df_add(df_add(df_mul(dfv(vp.a_hi[a], vp.a_lo[a]), x), df_mul(dfv(vp.b_hi[a], vp.b_lo[a]), y)),
-                    dfv(vp.c_hi[a], vp.c_lo[a]));
-    }
-    const df len = df_sqrt(df_add(df_add(df_mul(u[0], u[0]), df_mul(u[1], u[1])), df_mul(u[2], u[2])));
-    for (int a = 0; a < 3; ++a) d[a] = df_div(u[a], len);
-  } else {
-    for (int a = 0; a < 3; ++a) {
-      o[a] = df_add(df_add(dfv(vp.e_hi[a], vp.e_lo[a]), df_mul(dfv(vp.a_hi[a], vp.a_lo[a]), x)),
-                    df_mul(dfv(vp.b_hi[a], vp.b_lo[a]), y));
-      d[a] = dfv(vp.c_hi[a], vp.c_lo[a]);
-    }
-  }
-  const float zero3[3] = {0.0f, 0.0f, 0.0f};
-  const float N3[3] = {(float)f.gdims[0], (float)f.gdims[1], (float)f.gdims[2]};
-  const Slab g = slab_df(o, d, zero3, N3);
-  const df t_in = df_max(df_from(0.0f), g.t0);
-  if (g.miss || !df_lt(t_in, g.t1)) return;
-  const df dt = dfv(vp.dt_hi, vp.dt_lo);
-  const int n = first_index(t_in, dt, g.t1);
-  const float blo[3] = {(float)br.lo[0], (float)br.lo[1], (float)br.lo[2]};
-  const float bhi[3] = {(float)br.hi[0], (float)br.hi[1], (float)br.hi[2]};
-  const Slab b = slab_df(o, d, blo, bhi);
-  if (b.miss || !df_lt(b.t0, b.t1)) return;
-  int j0 = (b.t0.hi == -INFINITY) ? 0 : first_index(t_in, dt, b.t0);
-  int j1 = (b.t1.hi == INFINITY) ? n : first_index(t_in, dt, b.t1);
-  j0 = min(j0, n);
-  j1 = min(max(j1, j0), n);
-  if (j1 <= j0) return;
-
-  const int64_t pitch_y = (int64_t)br.mb[0] * 64;
-  const int64_t pitch_z = pitch_y * br.mb[1];
-  const int cmax[3] = {br.hi[0] - br.lo[0], br.hi[1] - br.lo[1], br.hi[2] - br.lo[2]};
-  const float s_q = br.scale, o_q = br.offs;
-  float step[3];
-  for (int a = 0; a < 3; ++a) step[a] = df_to_f(df_mul(dt, d[a]));
-  const float tau = vp.tau;
-  const float kmax_f = (float)(K - 1);
-
-  for (int j = j0; j < j1; j += 32) {
-    // chunk anchor in double-float: local ghosted coordinate minus 1/2
-    const df t = df_add(t_in, df_mul(df_from((float)j + 0.5f), dt));
-    int ib[3];
-    float fr[3];
-    for (int a = 0; a < 3; ++a) {
-      df p = df_add(o[a], df_mul(t, d[a]));
-      p = df_sub(p, df_from((float)(br.lo[a] - 1) + 0.5f));
-      float fl = floorf(p.hi);
-      df r = df_sub(p, df_from(fl));
-      if (r.hi < 0.0f) { fl -= 1.0f; r = df_add(r, df_from(1.0f)); }
-      ib[a] = (int)fl;
-      fr[a] = df_to_f(r);
-    }
-    const int kend = min(32, j1 - j);
-    for (int k = 0; k < kend; ++k) {
-      const float kf = (float)k;
-      int i0[3];
-      float w[3];
-      for (int a = 0; a < 3; ++a) {
-        const float u = __builtin_fmaf(kf, step[a], fr[a]);
-        const float fu = floorf(u);
-        w[a] = u - fu;
-        i0[a] = min(max(ib[a] + (int)fu, 0), cmax[a]);
-      }
-      int64_t ox[2], oy[2], oz[2];
-      for (int c = 0; c < 2; ++c) {
-        const int xx = i0[0] + c, yy = i0[1] + c, zz = i0[2] + c;
-        ox[c] = (int64_t)(xx >> 2) * 64 + sx_(xx & 3);
-        oy[c] = (int64_t)(yy >> 2) * pitch_y + sy_(yy & 3);
-        oz[c] = (int64_t)(zz >> 2) * pitch_z + sz_(zz & 3);
-      }
-      const int64_t base = br.offset;
-      float v[8];
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        v[c] = fetch<FMT>(f.pool, base + ox[c & 1] + oy[(c >> 1) & 1] + oz[c >> 2], s_q, o_q);
-      const float c00 = __builtin_fmaf(w[0], v[1] - v[0], v[0]);
-      const float c10 = __builtin_fmaf(w[0], v[3] - v[2], v[2]);
-      const float c01 = __builtin_fmaf(w[0], v[5] - v[4], v[4]);
-      const float c11 = __builtin_fmaf(w[0], v[7] - v[6], v[6]);
-      const float c0 = __builtin_fmaf(w[1], c10 - c00, c00);
-      const float c1 = __builtin_fmaf(w[1], c11 - c01, c01);
-      const float val = __builtin_fmaf(w[2], c1 - c0, c0);
-      float xt = __builtin_fmaf(val, tf_scale, tf_bias);
-      xt = fminf(fmaxf(xt, 0.0f), kmax_f);
-      const int it = min((int)xt, K - 2);
-      const float ft = xt - (float)it;
-      const float4 p0 = table[it];
-      const float4 p1 = table[it + 1];
-      const float4 col = make_float4(__builtin_fmaf(ft, p1.x - p0.x, p0.x), __builtin_fmaf(ft, p1.y - p0.y, p0.y),
-                                     __builtin_fmaf(ft, p1.z - p0.z, p0.z), __builtin_fmaf(ft, p1.w - p0.w, p0.w));
-      const float om = 1.0f - acc.w;
-      acc.x = __builtin_fmaf(om, col.x, acc.x);
-      acc.y = __builtin_fmaf(om, col.y, acc.y);
-      acc.z = __builtin_fmaf(om, col.z, acc.z);
-      acc.w = __builtin_fmaf(om, col.w, acc.w);
-      ++nsamp;
-      if (acc.w >= tau) return;
-    }
-  }
-}
-
-template <int FMT>
-__global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
-  const int lane = threadIdx.x & 63;
-  const BcFrameIn* fin = f.fin;
-  const int K = fin->K;
-  const float tf_scale = fin->tf_scale, tf_bias = fin->tf_bias;
-  const float4* table = reinterpret_cast<const float4*>(fin->table);
-  const int nv = f.n_views, nb = f.n_bricks;
-  const int KB = nb * nv;
-  const uint32_t n_items = f.ctr->n_items;
-  for (;;) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(&f.ctr->queue, 1u);
-    item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
-    if (item >= n_items) break;
-    int lo = 0, hi = KB;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if ((uint32_t)f.item_base[mid] <= item) lo = mid; else hi = mid;
-    }
-    const int b = lo / nv, v = lo % nv;
-    const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
-    const int tw = r[2] - r[0];
-    const int local = (int)(item - (uint32_t)f.item_base[lo]);
-    const int tx = r[0] + local % tw, ty = r[1] + local / tw;
-    const int px = tx * BC_TILE + (lane & (BC_TILE - 1));
-    const int py = ty * BC_TILE + (lane / BC_TILE);
-    const BcViewParams& vp = f.views[v];
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    uint32_t ns = 0;
-    if (px < vp.width && py < vp.height) {
-      const BcBrick br = f.bricks[b];
-      cast_ray<FMT>(f, vp, br, table, tf_scale, tf_bias, K, px, py, acc, ns);
-    }
-    f.sub[(int64_t)item * 64 + lane] = acc;
-    uint32_t tot = ns;
-    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-    if (lane == 0 && tot) {
-      atomicAdd(&f.ctr->nominal, (unsigned long long)tot);
-      atomicAdd(&f.ctr->evaluated, (unsigned long long)tot);
-    }
-  }
-}
-
 __global__ __launch_bounds__(64) void composite_kernel(BcFramePtrs f, float4* __restrict__ out) {
   const int v = blockIdx.z;
   const int tx = blockIdx.x, ty = blockIdx.y;
@@ -516,13 +293,6 @@ __global__ __launch_bounds__(64) void composite_kernel(BcFramePtrs f, float4* __
 
 hipError_t bc_launch_setup(const BcFramePtrs& f, hipStream_t st) {
   setup_kernel<<<1, 1024, 0, st>>>(f);
-  return hipGetLastError();
-}
-
-hipError_t bc_launch_render(const BcFramePtrs& f, int n_workgroups, hipStream_t st) {
-  if (f.storage == 0) render_kernel<0><<<n_workgroups, 256, 0, st>>>(f);
-  else if (f.storage == 1) render_kernel<1><<<n_workgroups, 256, 0, st>>>(f);
-  else render_kernel<2><<<n_workgroups, 256, 0, st>>>(f);
   return hipGetLastError();
 }
 

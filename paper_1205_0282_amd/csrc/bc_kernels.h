@@ -30,6 +30,9 @@ struct BcFramePtrs {
   BcCounters* ctr;
   float4* sub;            // sub-image tiles: [max_items][64]
   const void* pool;
+  uint32_t* occ;          // cell-occupancy bits of every brick
+  int32_t ess;            // skip samples in clear cells
+  int32_t K;              // transfer-function entries
   int32_t n_bricks, n_views;
   int32_t gdims[3];
   int64_t max_items;
@@ -38,5 +41,6 @@ struct BcFramePtrs {
 };
 
 hipError_t bc_launch_setup(const BcFramePtrs& f, hipStream_t st);
+hipError_t bc_launch_classify(const BcFramePtrs& f, int max_words, hipStream_t st);
 hipError_t bc_launch_render(const BcFramePtrs& f, int n_workgroups, hipStream_t st);
 hipError_t bc_launch_composite(const BcFramePtrs& f, float4* out, hipStream_t st);

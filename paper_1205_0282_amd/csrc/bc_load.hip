@@ -1,8 +1,8 @@
 // Load-time kernels: per-brick minimum/maximum of the stored values (the
 // paper's min/max task after the data reaches GPU memory, Section 2.3.1), the
 // FP8 scale/offset, and the encode + layout of ghosted bricks into 4x4x4
-// micro-blocks (voxels of a micro-block in Morton order, micro-blocks
-// row-major inside the brick).
+// micro-blocks (voxels of a micro-block x fastest, micro-blocks row-major
+// inside the brick).
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include "bc_types.h"
@@ -125,9 +125,9 @@ __global__ __launch_bounds__(256) void encode_kernel(SrcView s, const BcBrick* b
     const int mbx = (int)(mbi % br.mb[0]);
     const int mby = (int)((mbi / br.mb[0]) % br.mb[1]);
     const int mbz = (int)(mbi / ((int64_t)br.mb[0] * br.mb[1]));
-    const int wx = (in & 1) | ((in >> 2) & 2);
-    const int wy = ((in >> 1) & 1) | ((in >> 3) & 2);
-    const int wz = ((in >> 2) & 1) | ((in >> 4) & 2);
+    const int wx = in & 3;
+    const int wy = (in >> 2) & 3;
+    const int wz = in >> 4;
     // local ghosted index (0 <-> voxel lo-1); padding replicates the last ghost
     const int lx = min(mbx * 4 + wx, cx + 1);
     const int ly = min(mby * 4 + wy, cy + 1);

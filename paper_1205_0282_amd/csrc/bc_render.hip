@@ -1,0 +1,402 @@
+// Ray casting of bricks into sub-images (the per-GPU ray-casting step of
+// Sections 1.2 and 2.3.2) and the empty-space classification it uses.
+//
+//  classify  once per transfer-function table: one bit per interpolation cell
+//            of every brick (the cube between 2x2x2 neighbouring stored
+//            voxels) telling whether any value the cell can interpolate to
+//            maps to a non-zero table entry.  A sample in a clear cell adds
+//            exactly zero to its ray, so it is counted but not evaluated.
+//  render    persistent kernel: every wave pulls (brick, view, 8x8 tile) work
+//            items from a device counter and casts the tile's 64 rays
+//            through the brick: ray from the viewer's matrices, clipping to
+//            the cube and the brick, samples at a fixed step anchored at the
+//            cube entry, trilinear interpolation, transfer-function lookup,
+//            front-to-back compositing with early ray termination.
+//
+// Sample positions.  Per ray and brick the first sample's brick-local
+// position and the step vector are formed in double-float arithmetic and
+// turned into 32.32 fixed point; every later sample position is an exact
+// integer sum, so the cell index and the interpolation weights of sample j
+// carry about 2^-32 voxels of error however far the ray has travelled.
+//
+// Lane schedule.  Each lane walks its own ray in chunks of 32 samples.  For a
+// chunk it first gathers the 32 occupancy bits (cheap, all lanes in step),
+// then evaluates only the samples whose cell is occupied, lowest first, so a
+// lane's evaluations do not wait for the empty stretches of other lanes.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <float.h>
+#include "bc_types.h"
+#include "bc_kernels.h"
+#include "bc_df.h"
+
+namespace {
+
+// ------------------------------------------------------------------ storage
+template <int FMT>
+__device__ __forceinline__ float fetch(const void* __restrict__ pool, uint32_t idx, float s, float o) {
+  if (FMT == 0) return static_cast<const float*>(pool)[idx];
+  if (FMT == 1) return __half2float(static_cast<const __half*>(pool)[idx]);
+  const uint32_t c = static_cast<const uint8_t*>(pool)[idx];
+  const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+  float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
+  mag = (c & 0x80u) ? -mag : mag;
+  return __builtin_fmaf(mag, s, o);
+}
+
+// element index, inside the brick, of ghosted local voxel (x, y, z): 4x4x4
+// micro-blocks stored row-major, voxels of a micro-block x fastest
+__device__ __forceinline__ uint32_t vox_index(int x, int y, int z, int mbx, int mby) {
+  const uint32_t blk = (uint32_t)(x >> 2) + (uint32_t)mbx * ((uint32_t)(y >> 2) + (uint32_t)mby * (uint32_t)(z >> 2));
+  return (blk << 6) | ((uint32_t)(z & 3) << 4) | ((uint32_t)(y & 3) << 2) | (uint32_t)(x & 3);
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// ------------------------------------------------------------------ classify
+struct ClassifyArgs {
+  const BcBrick* bricks;
+  const BcFrameIn* fin;
+  uint32_t* occ;
+  const void* pool;
+  int32_t n_bricks;
+  int32_t max_words;      // largest occupancy word count of a brick
+};
+
+template <int FMT>
+__global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs a) {
+  __shared__ int32_t nzp[BC_MAX_K + 1];   // nzp[k] = non-zero table entries among the first k
+  __shared__ int32_t part[256];
+  const int K = a.fin->K;
+  const int tid = threadIdx.x;
+  // block-wide prefix count of entries with non-zero opacity (premultiplied
+  // colour is zero wherever opacity is)
+  const int per = (K + 255) / 256;
+  int cnt = 0;
+  for (int k = tid * per; k < min(K, (tid + 1) * per); ++k) cnt += a.fin->table[k][3] != 0.0f;
+  part[tid] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int i = 0; i < 256; ++i) { const int t = part[i]; part[i] = run; run += t; }
+  }
+  __syncthreads();
+  int run = part[tid];
+  for (int k = tid * per; k < min(K, (tid + 1) * per); ++k) {
+    nzp[k] = run;
+    run += a.fin->table[k][3] != 0.0f;
+  }
+  if (tid == 255) nzp[K] = run;
+  __syncthreads();
+  const float sc = a.fin->tf_scale, bi = a.fin->tf_bias, kmax = (float)(K - 1);
+
+  const int64_t total = (int64_t)a.n_bricks * a.max_words;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + tid; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(g / a.max_words);
+    const int w = (int)(g % a.max_words);
+    const BcBrick& br = a.bricks[b];
+    const int WX = br.occ_w[0], WY = br.occ_w[1], WZ = br.occ_w[2];
+    if (w >= WX * WY * WZ) continue;
+    const int wx = w % WX, wy = (w / WX) % WY, wz = w / (WX * WY);
+    // cells 0..ncell-1 per axis; cell i spans ghosted voxels i and i+1
+    const int ncx = br.hi[0] - br.lo[0] + 1, ncy = br.hi[1] - br.lo[1] + 1, ncz = br.hi[2] - br.lo[2] + 1;
+    const int vmax_x = ncx, vmax_y = ncy, vmax_z = ncz;   // last ghosted voxel index
+    float v[3][5][5];
+    const float s_q = br.scale, o_q = br.offs;
+    const void* pool = static_cast<const char*>(a.pool) + br.offset * (FMT == 0 ? 4 : (FMT == 1 ? 2 : 1));
+    for (int z = 0; z < 3; ++z)
+      for (int y = 0; y < 5; ++y)
+        for (int x = 0; x < 5; ++x) {
+          const int gx = clampi(wx * 4 + x, 0, vmax_x), gy = clampi(wy * 4 + y, 0, vmax_y),
+                    gz = clampi(wz * 2 + z, 0, vmax_z);
+          v[z][y][x] = fetch<FMT>(pool, vox_index(gx, gy, gz, br.mb[0], br.mb[1]), s_q, o_q);
+        }
+    uint32_t bits = 0;
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 4; ++cy)
+        for (int cx = 0; cx < 4; ++cx) {
+          if (wx * 4 + cx >= ncx || wy * 4 + cy >= ncy || wz * 2 + cz >= ncz) continue;
+          float lo = FLT_MAX, hi = -FLT_MAX;
+          for (int c = 0; c < 8; ++c) {
+            const float t = v[cz + (c >> 2)][cy + ((c >> 1) & 1)][cx + (c & 1)];
+            lo = fminf(lo, t);
+            hi = fmaxf(hi, t);
+          }
+          // trilinear values lie within the corner range up to a few roundings
+          const float m = fmaxf(fabsf(lo), fabsf(hi)) * 9.5367431640625e-07f + 1e-30f;   // 2^-20
+          float xl = __builtin_fmaf(lo - m, sc, bi), xh = __builtin_fmaf(hi + m, sc, bi);
+          xl = fminf(fmaxf(xl, 0.0f), kmax);
+          xh = fminf(fmaxf(xh, 0.0f), kmax);
+          const int il = min((int)xl, K - 2), ih = min((int)xh, K - 2) + 1;
+          if (nzp[ih + 1] - nzp[il] > 0) bits |= 1u << ((cz << 4) | (cy << 2) | cx);
+        }
+    a.occ[br.occ_offset + w] = bits;
+  }
+}
+
+// ------------------------------------------------------------------ rays
+__device__ __forceinline__ df dfv(float hi, float lo) { return df_make(hi, lo); }
+
+// smallest j >= 0 with t_in + (j + 1/2) dt >= t
+__device__ __forceinline__ int first_index(df t_in, df dt, df t) {
+  const df q = df_div(df_sub(t, t_in), dt);
+  float jf = ceilf(df_to_f(q) - 0.5f);
+  int j = (int)fmaxf(jf, 0.0f);
+  // exact fix-up against the sample-time formula
+  for (int it = 0; it < 3; ++it) {
+    const df tj = df_add(t_in, df_mul(df_from((float)j + 0.5f), dt));
+    if (df_lt(tj, t)) { ++j; continue; }
+    if (j > 0) {
+      const df tm = df_add(t_in, df_mul(df_from((float)j - 0.5f), dt));
+      if (df_ge(tm, t)) { --j; continue; }
+    }
+    break;
+  }
+  return j;
+}
+
+struct Slab { df t0, t1; bool miss; };
+
+__device__ __forceinline__ Slab slab_df(const df* o, const df* d, const float* lo, const float* hi) {
+  Slab s;
+  s.t0 = df_from(-INFINITY);
+  s.t1 = df_from(INFINITY);
+  s.miss = false;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a].hi == 0.0f && d[a].lo == 0.0f) {
+      const bool in = df_ge(o[a], df_from(lo[a])) && df_lt(o[a], df_from(hi[a]));
+      if (!in) s.miss = true;
+      continue;
+    }
+    const df ta = df_div(df_sub(df_from(lo[a]), o[a]), d[a]);
+    const df tb = df_div(df_sub(df_from(hi[a]), o[a]), d[a]);
+    s.t0 = df_max(s.t0, df_min(ta, tb));
+    s.t1 = df_min(s.t1, df_max(ta, tb));
+  }
+  return s;
+}
+
+// 32.32 fixed point of a double-float (each part truncated; error < 2^-31)
+__device__ __forceinline__ int64_t q32(df a) {
+  return (int64_t)(a.hi * 4294967296.0f) + (int64_t)(a.lo * 4294967296.0f);
+}
+
+struct RaySeg {
+  int n;                 // samples of the ray inside the brick
+  int64_t u[3];          // first sample, ghosted brick-local coordinate minus 1/2, 32.32
+  int64_t s[3];          // step vector, 32.32
+};
+
+// Ray of pixel (px, py) against brick br: the samples t_j = t_in + (j+1/2) dt
+// of the ray's cube interval that fall in the brick's half-open box.
+__device__ bool ray_segment(const BcViewParams& vp, const int32_t* gdims, const BcBrick& br, int px, int py,
+                            RaySeg& seg) {
+  const int W = vp.width, H = vp.height;
+  const df x = df_div(df_from((float)(2 * px + 1 - W)), df_from((float)W));
+  const df y = df_div(df_from((float)(H - 2 * py - 1)), df_from((float)H));
+  df o[3], d[3];
+  if (vp.kind == 0) {
+    df u[3];
+    for (int a = 0; a < 3; ++a) {
+      o[a] = dfv(vp.e_hi[a], vp.e_lo[a]);
+      u[a] = df_add(df_add(df_mul(dfv(vp.a_hi[a], vp.a_lo[a]), x), df_mul(dfv(vp.b_hi[a], vp.b_lo[a]), y)),
+                    dfv(vp.c_hi[a], vp.c_lo[a]));
+    }
+    const df len = df_sqrt(df_add(df_add(df_mul(u[0], u[0]), df_mul(u[1], u[1])), df_mul(u[2], u[2])));
+    for (int a = 0; a < 3; ++a) d[a] = df_div(u[a], len);
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      o[a] = df_add(df_add(dfv(vp.e_hi[a], vp.e_lo[a]), df_mul(dfv(vp.a_hi[a], vp.a_lo[a]), x)),
+                    df_mul(dfv(vp.b_hi[a], vp.b_lo[a]), y));
+      d[a] = dfv(vp.c_hi[a], vp.c_lo[a]);
+    }
+  }
+  const float zero3[3] = {0.0f, 0.0f, 0.0f};
+  const float N3[3] = {(float)gdims[0], (float)gdims[1], (float)gdims[2]};
+  const Slab g = slab_df(o, d, zero3, N3);
+  const df t_in = df_max(df_from(0.0f), g.t0);
+  if (g.miss || !df_lt(t_in, g.t1)) return false;
+  const df dt = dfv(vp.dt_hi, vp.dt_lo);
+  const int n = first_index(t_in, dt, g.t1);
+  const float blo[3] = {(float)br.lo[0], (float)br.lo[1], (float)br.lo[2]};
+  const float bhi[3] = {(float)br.hi[0], (float)br.hi[1], (float)br.hi[2]};
+  const Slab b = slab_df(o, d, blo, bhi);
+  if (b.miss || !df_lt(b.t0, b.t1)) return false;
+  int j0 = (b.t0.hi == -INFINITY) ? 0 : first_index(t_in, dt, b.t0);
+  int j1 = (b.t1.hi == INFINITY) ? n : first_index(t_in, dt, b.t1);
+  j0 = min(j0, n);
+  j1 = min(max(j1, j0), n);
+  if (j1 <= j0) return false;
+  seg.n = j1 - j0;
+  const df t0 = df_add(t_in, df_mul(df_from((float)j0 + 0.5f), dt));
+  for (int a = 0; a < 3; ++a) {
+    const df p = df_add(o[a], df_mul(t0, d[a]));
+    seg.u[a] = q32(df_sub(p, df_from((float)br.lo[a] - 0.5f)));
+    seg.s[a] = q32(df_mul(dt, d[a]));
+  }
+  return true;
+}
+
+__device__ __forceinline__ int hi32(int64_t v) { return (int)(v >> 32); }
+__device__ __forceinline__ float frac32(int64_t v) { return (float)(uint32_t)v * 2.3283064365386963e-10f; }
+
+// ------------------------------------------------------------------ render
+template <int FMT, bool TF_LDS>
+__global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
+  __shared__ float4 s_tab[TF_LDS ? BC_TF_LDS : 1];
+  const int lane = threadIdx.x & 63;
+  const BcFrameIn* fin = f.fin;
+  const int K = fin->K;
+  const float tf_scale = fin->tf_scale, tf_bias = fin->tf_bias;
+  const float kmax_f = (float)(K - 1);
+  const float4* gtab = reinterpret_cast<const float4*>(fin->table);
+  if (TF_LDS) {
+    for (int k = threadIdx.x; k < K; k += blockDim.x) s_tab[k] = gtab[k];
+    __syncthreads();
+  }
+  const float4* tab = TF_LDS ? s_tab : gtab;
+  const int nv = f.n_views, nb = f.n_bricks;
+  const int KB = nb * nv;
+  const uint32_t n_items = f.ctr->n_items;
+  const bool ess = f.ess != 0;
+  uint64_t nominal = 0, evaluated = 0;
+  for (;;) {
+    uint32_t item = 0;
+    if (lane == 0) item = atomicAdd(&f.ctr->queue, 1u);
+    item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
+    if (item >= n_items) break;
+    int lo = 0, hi = KB;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if ((uint32_t)f.item_base[mid] <= item) lo = mid; else hi = mid;
+    }
+    const int b = lo / nv, v = lo % nv;
+    const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
+    const int tw = r[2] - r[0];
+    const int local = (int)(item - (uint32_t)f.item_base[lo]);
+    const int tx = r[0] + local % tw, ty = r[1] + local / tw;
+    const int px = tx * BC_TILE + (lane & (BC_TILE - 1));
+    const int py = ty * BC_TILE + (lane / BC_TILE);
+    const BcViewParams& vp = f.views[v];
+    const BcBrick& br = f.bricks[b];
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    RaySeg seg;
+    if (px < vp.width && py < vp.height && ray_segment(vp, f.gdims, br, px, py, seg)) {
+      const float tau = vp.tau;
+      const int cmx = br.hi[0] - br.lo[0], cmy = br.hi[1] - br.lo[1], cmz = br.hi[2] - br.lo[2];
+      const int mbx = br.mb[0], mby = br.mb[1];
+      const int WX = br.occ_w[0], WY = br.occ_w[1];
+      const uint32_t* __restrict__ occ = f.occ + br.occ_offset;
+      const int esz = FMT == 0 ? 4 : (FMT == 1 ? 2 : 1);
+      const void* __restrict__ pool = static_cast<const char*>(f.pool) + br.offset * esz;
+      const float s_q = br.scale, o_q = br.offs;
+      const uint32_t dxb = 61u, dyb = (uint32_t)mbx * 64u - 12u, dzb = (uint32_t)mbx * (uint32_t)mby * 64u - 48u;
+      int64_t uc0 = seg.u[0], uc1 = seg.u[1], uc2 = seg.u[2];
+      const int64_t s0 = seg.s[0], s1 = seg.s[1], s2 = seg.s[2];
+      int used = seg.n;
+      for (int k = 0; k < seg.n; k += 32) {
+        const int cnt = min(32, seg.n - k);
+        uint32_t mask = cnt == 32 ? 0xffffffffu : ((1u << cnt) - 1u);
+        int64_t un0 = uc0, un1 = uc1, un2 = uc2;
+        if (ess) {
+          uint32_t m = 0;
+#pragma unroll
+          for (int i = 0; i < 32; ++i) {
+            const int ix = clampi(hi32(un0), 0, cmx), iy = clampi(hi32(un1), 0, cmy), iz = clampi(hi32(un2), 0, cmz);
+            const uint32_t w = (uint32_t)(ix >> 2) + (uint32_t)WX * ((uint32_t)(iy >> 2) + (uint32_t)WY * (uint32_t)(iz >> 1));
+            const uint32_t bit = (uint32_t)(ix & 3) | ((uint32_t)(iy & 3) << 2) | ((uint32_t)(iz & 1) << 4);
+            m |= ((occ[w] >> bit) & 1u) << i;
+            un0 += s0; un1 += s1; un2 += s2;
+          }
+          mask &= m;
+        } else {
+          un0 += 32 * s0; un1 += 32 * s1; un2 += 32 * s2;
+        }
+        bool stop = false;
+        while (mask) {
+          const int i = __builtin_ctz(mask);
+          mask &= mask - 1u;
+          const int64_t p0 = uc0 + (int64_t)i * s0, p1 = uc1 + (int64_t)i * s1, p2 = uc2 + (int64_t)i * s2;
+          const int ix = clampi(hi32(p0), 0, cmx), iy = clampi(hi32(p1), 0, cmy), iz = clampi(hi32(p2), 0, cmz);
+          const float wx = frac32(p0), wy = frac32(p1), wz = frac32(p2);
+          const uint32_t a000 = vox_index(ix, iy, iz, mbx, mby);
+          const uint32_t dx = (ix & 3) == 3 ? dxb : 1u;
+          const uint32_t dy = (iy & 3) == 3 ? dyb : 4u;
+          const uint32_t dz = (iz & 3) == 3 ? dzb : 16u;
+          const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
+          const float v000 = fetch<FMT>(pool, a000, s_q, o_q), v100 = fetch<FMT>(pool, a000 + dx, s_q, o_q);
+          const float v010 = fetch<FMT>(pool, a010, s_q, o_q), v110 = fetch<FMT>(pool, a010 + dx, s_q, o_q);
+          const float v001 = fetch<FMT>(pool, a001, s_q, o_q), v101 = fetch<FMT>(pool, a001 + dx, s_q, o_q);
+          const float v011 = fetch<FMT>(pool, a011, s_q, o_q), v111 = fetch<FMT>(pool, a011 + dx, s_q, o_q);
+          const float c00 = __builtin_fmaf(wx, v100 - v000, v000);
+          const float c10 = __builtin_fmaf(wx, v110 - v010, v010);
+          const float c01 = __builtin_fmaf(wx, v101 - v001, v001);
+          const float c11 = __builtin_fmaf(wx, v111 - v011, v011);
+          const float c0 = __builtin_fmaf(wy, c10 - c00, c00);
+          const float c1 = __builtin_fmaf(wy, c11 - c01, c01);
+          const float val = __builtin_fmaf(wz, c1 - c0, c0);
+          float xt = __builtin_fmaf(val, tf_scale, tf_bias);
+          xt = fminf(fmaxf(xt, 0.0f), kmax_f);
+          const int it = min((int)xt, K - 2);
+          const float ft = xt - (float)it;
+          const float4 q0 = tab[it];
+          const float4 q1 = tab[it + 1];
+          const float om = 1.0f - acc.w;
+          acc.x = __builtin_fmaf(om, __builtin_fmaf(ft, q1.x - q0.x, q0.x), acc.x);
+          acc.y = __builtin_fmaf(om, __builtin_fmaf(ft, q1.y - q0.y, q0.y), acc.y);
+          acc.z = __builtin_fmaf(om, __builtin_fmaf(ft, q1.z - q0.z, q0.z), acc.z);
+          acc.w = __builtin_fmaf(om, __builtin_fmaf(ft, q1.w - q0.w, q0.w), acc.w);
+          ++evaluated;
+          if (acc.w >= tau) {
+            used = k + i + 1;
+            stop = true;
+            break;
+          }
+        }
+        if (stop) break;
+        uc0 = un0; uc1 = un1; uc2 = un2;
+      }
+      nominal += (uint64_t)used;
+    }
+    f.sub[(int64_t)item * 64 + lane] = acc;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    nominal += __shfl_xor(nominal, off);
+    evaluated += __shfl_xor(evaluated, off);
+  }
+  if (lane == 0 && nominal) {
+    atomicAdd(&f.ctr->nominal, (unsigned long long)nominal);
+    atomicAdd(&f.ctr->evaluated, (unsigned long long)evaluated);
+  }
+}
+
+template <int FMT>
+hipError_t launch_render_fmt(const BcFramePtrs& f, int n_workgroups, hipStream_t st) {
+  if (f.K <= BC_TF_LDS) render_kernel<FMT, true><<<n_workgroups, 256, 0, st>>>(f);
+  else render_kernel<FMT, false><<<n_workgroups, 256, 0, st>>>(f);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t bc_launch_classify(const BcFramePtrs& f, int max_words, hipStream_t st) {
+  ClassifyArgs a;
+  a.bricks = f.bricks;
+  a.fin = f.fin;
+  a.occ = f.occ;
+  a.pool = f.pool;
+  a.n_bricks = f.n_bricks;
+  a.max_words = max_words;
+  const int64_t total = (int64_t)f.n_bricks * max_words;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  if (f.storage == 0) classify_kernel<0><<<grid, 256, 0, st>>>(a);
+  else if (f.storage == 1) classify_kernel<1><<<grid, 256, 0, st>>>(a);
+  else classify_kernel<2><<<grid, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t bc_launch_render(const BcFramePtrs& f, int n_workgroups, hipStream_t st) {
+  if (f.storage == 0) return launch_render_fmt<0>(f, n_workgroups, st);
+  if (f.storage == 1) return launch_render_fmt<1>(f, n_workgroups, st);
+  return launch_render_fmt<2>(f, n_workgroups, st);
+}

@@ -7,6 +7,7 @@
 #define BC_MAX_K 4096
 #define BC_TILE 8          // screen tile edge (pixels): one wave of 64 rays per work item
 #define BC_MB 4            // micro-block edge (voxels): 64 voxels stored contiguously
+#define BC_TF_LDS 1024     // transfer functions up to this many entries are staged in LDS
 
 // A rendering request as the viewer sends it (FP64, OpenGL column-major).
 struct BcViewIn {
@@ -51,6 +52,9 @@ struct BcBrick {
   int32_t gdim[3];           // stored dims: core + 2 ghosts, padded to a multiple of 4
   int32_t mb[3];             // micro-blocks per axis
   int64_t offset;            // first element of the brick in the pool
+  int64_t occ_offset;        // first 32-bit word of the brick's cell-occupancy bits
+  int32_t occ_w[3];          // occupancy words per axis (one word = 4 x 4 x 2 cells)
+  int32_t pad_;
   float scale, offs;         // decode v = q * scale + offs (FP8); 1, 0 otherwise
   float vmin, vmax;          // range of the stored (core + ghost) values
 };

@@ -15,7 +15,7 @@ def cam_of(v: synth.ViewSpec) -> rc.Camera:
 
 
 def gpu_render(vol, brick, views, tf_rgba, vmin, vmax, storage="f32", src="device", max_tiles=0,
-               keep=False):
+               keep=False, options=None):
     import torch
     dims = vol.shape[::-1]
     bc = binding.BrickCaster(0)
@@ -29,6 +29,8 @@ def gpu_render(vol, brick, views, tf_rgba, vmin, vmax, storage="f32", src="devic
         del t
     else:
         bc.load(np.ascontiguousarray(vol))
+    for k, val in (options or {}).items():
+        bc.set_option(k, val)
     bc.set_transfer_function(tf_rgba, vmin, vmax)
     bc.set_views(views)
     out = bc.render()

@@ -172,3 +172,32 @@ def test_batched_views_equal_single_views_and_repeat(small_cube):
     for i, v in enumerate(views):
         single = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax)
         assert np.array_equal(single[0], batch[i])
+
+
+@pytest.mark.parametrize("storage", ["f32", "fp8"])
+def test_empty_space_skipping_is_bit_identical(small_cube, storage):
+    """Skipping samples in cells whose values map to zero-opacity entries
+    changes nothing in the image and only lowers the evaluated count."""
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    views = [synth.orbit_view(vol.shape[::-1], f, kind="persp", width=160, height=120) for f in (5, 37)]
+    on, bc_on = gpu_render(vol, (48, 40, 64), views, rgba, vmin, vmax, storage=storage, keep=True,
+                           options={binding.BC_OPT_EMPTY_SKIP: 1})
+    off, bc_off = gpu_render(vol, (48, 40, 64), views, rgba, vmin, vmax, storage=storage, keep=True,
+                             options={binding.BC_OPT_EMPTY_SKIP: 0})
+    assert np.array_equal(on, off)
+    s_on, s_off = bc_on.stats(), bc_off.stats()
+    assert s_on["nominal_samples"] == s_off["nominal_samples"]
+    assert s_off["evaluated_samples"] == s_off["nominal_samples"]
+    assert s_on["evaluated_samples"] < 0.5 * s_on["nominal_samples"]
+    # a new table (different opacity) re-classifies the cells
+    rgba2 = rgba.copy()
+    rgba2[:, 3] = np.where(rgba2[:, 3] > 0, rgba2[:, 3], 0.02)
+    bc_on.set_transfer_function(rgba2, vmin, vmax)
+    bc_off.set_transfer_function(rgba2, vmin, vmax)
+    a = bc_on.render().cpu().numpy()
+    b = bc_off.render().cpu().numpy()
+    assert np.array_equal(a, b)
+    assert bc_on.stats()["evaluated_samples"] == bc_on.stats()["nominal_samples"]
+    bc_on.close()
+    bc_off.close()
