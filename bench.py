@@ -67,6 +67,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target wall time of the oracle sample (0 disables the CPU baseline)")
     p.add_argument("--cpu-workers", type=int, default=0, help="0 = all host cores, at most 16")
+    p.add_argument("--frames", type=int, default=ORBIT,
+                   help="distinct orbit frames cycled through (the first N of the 64-frame orbit)")
+    p.add_argument("--check-pixels", type=int, default=1024,
+                   help="sampled pixels of frame 0 compared with the FP64 oracle on the FP32 cube (0 disables)")
     return p.parse_args()
 
 
@@ -86,6 +90,51 @@ def _cpu_chunk(pix):
     t0 = time.perf_counter()
     res = rc.render_bricked(c["stored"], c["dims"], c["cam"], c["tf"], 0.5, 0.99, pixels=pix)
     return int(res.samples.sum()), time.perf_counter() - t0
+
+
+def _ref_chunk(pix):
+    """Oracle pixels (main result and near-tie branches) for the precision check."""
+    from oracle import raycast as rc
+    c = _CPU
+    res = rc.render_bricked(c["stored"], c["dims"], c["cam"], c["tf"], 0.5, 0.99, pixels=pix)
+    return res.image, {int(k): v for k, v in res.branches.items()}
+
+
+def oracle_reference(vol, recipe, brick, view, rgba, vmin, vmax, n_px, workers):
+    """FP64 oracle on the FP32 cube at a seeded sample of hit pixels of one frame."""
+    from oracle import raycast as rc
+    dims = recipe.dims
+    _CPU.update(stored=rc.store_bricks(vol, rc.brick_grid(dims, (brick,) * 3)), dims=dims,
+                cam=rc.Camera(view.modelview, view.projection, view.width, view.height),
+                tf=rc.TransferFunction(rgba, vmin, vmax))
+    cam = _CPU["cam"]
+    rng = np.random.default_rng(777)
+    cand = np.stack([rng.integers(0, view.width, 8 * n_px), rng.integers(0, view.height, 8 * n_px)], axis=1)
+    o, d = cam.rays(cand[:, 0], cand[:, 1])
+    _, _, hit = rc.global_interval(o, d, dims)
+    pix = cand[hit][:n_px]
+    chunks = np.array_split(pix, workers * 2)
+    with mp.get_context("fork").Pool(workers) as pool:
+        out = pool.map(_ref_chunk, chunks)
+    img = np.concatenate([o[0] for o in out])
+    branches, base = {}, 0
+    for (im, br), ch in zip(out, chunks):
+        for k, v in br.items():
+            branches[base + k] = v
+        base += len(ch)
+    _CPU.clear()
+    return pix, img, branches
+
+
+def precision_report(gpu_px, ref_img, branches):
+    """max |GPU - oracle| (near-tie rays: closest branch) and PSNR (peak 1)."""
+    err = np.max(np.abs(gpu_px - ref_img), axis=1)
+    for r, alts in branches.items():
+        if alts:
+            err[r] = min(err[r], min(float(np.max(np.abs(gpu_px[r] - a))) for a in alts))
+    mse = float(np.mean((gpu_px - ref_img) ** 2))
+    return {"pixels": int(len(ref_img)), "max_abs": float(err.max()),
+            "psnr_db": (float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)), "near_tie_rays": len(branches)}
 
 
 def cpu_baseline(vol, recipe, brick, view, rgba, vmin, vmax, seconds, workers):
@@ -127,11 +176,17 @@ def main():
     vmin, vmax = float(vol.min()), float(vol.max())
     log(f"cube {recipe.dims} generated in {time.perf_counter() - t:.1f} s; range [{vmin:.3f}, {vmax:.3f}]")
     rgba = synth.ramp_tf(vmin, vmax)
-    views = views_for(recipe, W, H)
+    views = views_for(recipe, W, H)[:max(1, min(ORBIT, args.frames))]
+    nf = len(views)
 
+    workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+    ref = None
+    if args.check_pixels > 0:
+        t = time.perf_counter()
+        ref = oracle_reference(vol, recipe, brick, views[0], rgba, vmin, vmax, args.check_pixels, workers)
+        log(f"oracle reference: {len(ref[0])} pixels of frame 0 in {time.perf_counter() - t:.1f} s")
     cpu = None
     if args.cpu_seconds > 0:
-        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
         cpu = cpu_baseline(vol, recipe, brick, views[0], rgba, vmin, vmax, args.cpu_seconds, workers)
         log(f"cpu baseline: {cpu['value'] * 1e3:.4f} Msamples/s on {cpu['cores']} processes")
 
@@ -170,15 +225,23 @@ def main():
         algo_bytes.append(int(core_bytes[live].sum()) + st["n_tiles"] * 64 * 16)
     log(f"orbit: mean {np.mean(samples) / 1e6:.1f} M samples/frame, {np.mean(tiles):.0f} tiles/frame")
 
+    precision = None
+    if ref is not None:
+        pix, ref_img, branches = ref
+        bc.set_views([views[0]])
+        img = bc.render(out)[0].cpu().numpy().astype(np.float64)
+        precision = precision_report(img[pix[:, 1], pix[:, 0]], ref_img, branches)
+        log(f"precision vs FP64 oracle: {precision}")
+
     for i in range(args.warmup):
-        bc.set_views([views[i % ORBIT]])
+        bc.set_views([views[i % nf]])
         bc.render(out)
     torch.cuda.synchronize()
     bc.enable_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        bc.set_views([views[i % ORBIT]])
+        bc.set_views([views[i % nf]])
         bc.render(out)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -186,7 +249,7 @@ def main():
     bc.enable_timing(False)
     assert n_timed == args.steps, (n_timed, args.steps)
 
-    idx = [i % ORBIT for i in range(args.steps)]
+    idx = [i % nf for i in range(args.steps)]
     tot_samples = float(sum(samples[i] for i in idx))
     tot_bytes = float(sum(algo_bytes[i] for i in idx))
     render_s = stage_ms[1] / 1e3
@@ -209,7 +272,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cube": list(recipe.dims), "brick": brick,
                    "image": [W, H], "step_vox": 0.5, "ert": 0.99, "storage": args.storage,
-                   "orbit_frames": ORBIT, "views_per_launch": 1},
+                   "orbit_frames": nf, "views_per_launch": 1},
         "stage_ms_per_frame": {"setup": stage_ms[0] / n_timed, "render": stage_ms[1] / n_timed,
                                "composite": stage_ms[2] / n_timed},
         "samples_per_frame": tot_samples / args.steps,
@@ -217,6 +280,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "render_kernel", "algo_bytes_per_launch": tot_bytes / args.steps},
+        "precision_vs_oracle": precision,
         "cpu_baseline": cpu,
     }
     bc.close()

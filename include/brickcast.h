@@ -89,7 +89,8 @@ typedef struct {
  *                                one occupancy bit per interpolation cell of every brick)
  *   bytes_out[2] sub-images     (max_tiles sub-image tiles of 8x8 RGBA float32)
  *   bytes_out[3] load scratch   (one brick's source region, used when the source is on the host)
- * max_tiles = 0 picks a default bound: views * screen tiles * min(bricks,
+ * max_tiles = 0 picks a default bound: views * screen tiles * bricks when
+ * that is at most 2^18 tiles, else views * screen tiles * min(bricks,
  * 2 * (bricks along x + along y + along z) + 4).  Every region is 256-byte aligned by the caller.
  * Errors: BC_E_ARG for null pointers, non-positive dims, a share outside the
  * cube, ghost != 1, unknown storage/src_dtype, max_views not in [1, 4],
@@ -148,11 +149,28 @@ int bc_set_view(bc_ctx* ctx, const bc_view* views, int n_views);
  * missing; BC_E_ARG for a null or misaligned out. */
 int bc_render_frame(bc_ctx* ctx, float* out, void* stream);
 
+/* Learned frames (enable = 1; needs the upsampler workspace and weights, see
+ * bc_cnn_* below, and an even frame width and height).  A learned frame
+ * renders the views at half the width and height with step `coarse_step`
+ * (voxels; opacity corrected for that step), upsamples them with the network
+ * into `out`, then renders plain (full size, the views' own step) one screen
+ * tile of every validate_stride x validate_stride block of tiles (the chosen
+ * tile moves from frame to frame) and compares: if the PSNR (peak 1, over the
+ * RGBA of those tiles) is below psnr_threshold_db the whole frame is
+ * re-rendered plain into `out` on the device, with no host round trip.  The
+ * decision is in bc_get_frame_stats.  With timing enabled the three stage
+ * times of a learned frame are: coarse render, network, validation plus any
+ * fall-back.  Errors: BC_E_ARG for enable not 0/1, coarse_step <= 0, a
+ * non-finite threshold, validate_stride outside [1, 64]. */
+int bc_set_learned(bc_ctx* ctx, int enable, double coarse_step, double psnr_threshold_db, int validate_stride);
+
 /* Statistics of the last frame; waits for it to finish. */
 typedef struct {
   uint64_t nominal_samples;    /* samples composited, up to termination, skipped-empty ones included */
   uint64_t evaluated_samples;  /* samples actually interpolated and looked up */
-  uint32_t n_tiles;            /* (brick, view, 8x8 tile) work items of the frame */
+  uint32_t n_tiles;            /* (brick, view, 8x8 tile) work items of all passes of the frame */
+  int32_t fell_back;           /* learned frame: 1 if it was re-rendered plain, else 0; -1 for a plain frame */
+  float psnr_db;               /* learned frame: PSNR (peak 1) of the validation tiles; NaN for a plain frame */
   uint32_t reserved;
 } bc_frame_stats;
 int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);

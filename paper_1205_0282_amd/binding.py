@@ -25,7 +25,7 @@ EXPORTS = [
     "bc_get_bricks", "bc_get_visibility_order", "bc_get_rects", "bc_read_brick",
     "bc_enable_timing", "bc_get_timing", "bc_set_option",
     "bc_cnn_plan", "bc_cnn_bind", "bc_cnn_set_weights", "bc_cnn_get_weights", "bc_cnn_forward",
-    "bc_cnn_gradients", "bc_cnn_train_step",
+    "bc_cnn_gradients", "bc_cnn_train_step", "bc_set_learned",
 ]
 CNN_N_PARAMS = 15056
 BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS = 0, 1
@@ -54,7 +54,8 @@ class View(C.Structure):
 
 class FrameStats(C.Structure):
     _fields_ = [("nominal_samples", C.c_uint64), ("evaluated_samples", C.c_uint64),
-                ("n_tiles", C.c_uint32), ("reserved", C.c_uint32)]
+                ("n_tiles", C.c_uint32), ("fell_back", C.c_int32), ("psnr_db", C.c_float),
+                ("reserved", C.c_uint32)]
 
 
 _LIB = None
@@ -86,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "bc_enable_timing": (I, [P, I]),
         "bc_set_option": (I, [P, I, I64]),
         "bc_cnn_plan": (I, [P, I, I, I, C.POINTER(C.c_size_t)]),
+        "bc_set_learned": (I, [P, I, D, D, I]),
         "bc_cnn_bind": (I, [P, P, C.c_size_t]),
         "bc_cnn_set_weights": (I, [P, C.POINTER(F), C.POINTER(F), C.POINTER(F), C.c_size_t, I64]),
         "bc_cnn_get_weights": (I, [P, C.POINTER(F), C.POINTER(F), C.POINTER(F), C.c_size_t, C.POINTER(I64)]),
@@ -218,7 +220,7 @@ class BrickCaster:
         s = FrameStats()
         self._check(self.lib.bc_get_frame_stats(self.h, C.byref(s)))
         return {"nominal_samples": int(s.nominal_samples), "evaluated_samples": int(s.evaluated_samples),
-                "n_tiles": int(s.n_tiles)}
+                "n_tiles": int(s.n_tiles), "fell_back": int(s.fell_back), "psnr_db": float(s.psnr_db)}
 
     def set_option(self, option, value):
         self._check(self.lib.bc_set_option(self.h, int(option), int(value)))
@@ -233,6 +235,10 @@ class BrickCaster:
         n = C.c_int()
         self._check(self.lib.bc_get_timing(self.h, ms, C.byref(n)))
         return [float(x) for x in ms], int(n.value)
+
+    def set_learned(self, enable=True, coarse_step=2.0, psnr_threshold_db=40.0, validate_stride=8):
+        self._check(self.lib.bc_set_learned(self.h, 1 if enable else 0, float(coarse_step),
+                                            float(psnr_threshold_db), int(validate_stride)))
 
     # -------------------------------------------------------- upsampler
     def cnn_setup(self, max_n, max_h, max_w):

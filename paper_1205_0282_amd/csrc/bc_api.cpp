@@ -24,6 +24,7 @@ thread_local std::string g_create_error;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kMaxTimedFrames = 4096;
+constexpr int kPasses = 3;   // learned frame: coarse, validation, conditional plain
 
 }  // namespace
 
@@ -45,7 +46,7 @@ struct bc_ctx {
          off_ctr = 0, off_occ = 0;
   int max_occ_words = 0;
   void* dev[4] = {nullptr, nullptr, nullptr, nullptr};
-  // per-frame input ring (pinned host memory) and events
+  // per-frame input ring (pinned host memory, kPasses pass inputs per slot) and events
   BcFrameIn* pinned[2] = {nullptr, nullptr};
   hipEvent_t copy_done[2] = {nullptr, nullptr};
   bool copy_pending[2] = {false, false};
@@ -74,6 +75,12 @@ struct bc_ctx {
   char* cnn_ws = nullptr;
   int64_t cnn_step = 0;
   std::vector<float> cnn_loss_host;
+  // learned frames: coarse render + upsampler, validated on a sparse set of
+  // tiles rendered plain; falls back to the plain render below the threshold
+  bool learned = false, last_learned = false;
+  double coarse_step = 2.0, psnr_threshold = 40.0;
+  int val_stride = 8;
+  uint64_t frame_counter = 0;
   // per-stage timing: 4 events per frame (before setup, before render, before
   // composite, after composite) recorded on the frame's stream
   bool timing = false;
@@ -225,6 +232,98 @@ int wait_frame(bc_ctx* c) {
   return BC_OK;
 }
 
+struct PassSpec {
+  int width, height;
+  double step;
+  int stride, ox, oy;
+  bool reset, conditional;
+};
+
+// per-pass input: the views at the pass's size and step, the opacity-corrected
+// premultiplied table for that step, and the tile selection
+void fill_pass(bc_ctx* c, BcFrameIn* fin, const PassSpec& p) {
+  const int n = (int)c->views.size();
+  for (int i = 0; i < n; ++i) {
+    BcViewIn& vi = fin->views[i];
+    std::memcpy(vi.mv, c->views[i].modelview, sizeof vi.mv);
+    std::memcpy(vi.pr, c->views[i].projection, sizeof vi.pr);
+    vi.width = p.width;
+    vi.height = p.height;
+    vi.step = p.step;
+    vi.tau = c->views[i].ert_threshold;
+  }
+  fin->n_views = n;
+  fin->K = c->K;
+  const double scale = (c->K - 1) / (c->vmax - c->vmin);
+  fin->tf_scale = (float)scale;
+  fin->tf_bias = (float)(-c->vmin * scale);
+  fin->tile_stride = p.stride;
+  fin->tile_ox = p.ox;
+  fin->tile_oy = p.oy;
+  fin->reset_counters = p.reset ? 1 : 0;
+  fin->conditional = p.conditional ? 1 : 0;
+  fin->psnr_threshold = (float)c->psnr_threshold;
+  for (int k = 0; k < c->K; ++k) {
+    const double a = c->tf[4 * k + 3];
+    const double ac = 1.0 - std::pow(1.0 - a, p.step / c->dt_ref);
+    fin->table[k][0] = (float)(ac * c->tf[4 * k + 0]);
+    fin->table[k][1] = (float)(ac * c->tf[4 * k + 1]);
+    fin->table[k][2] = (float)(ac * c->tf[4 * k + 2]);
+    fin->table[k][3] = (float)ac;
+  }
+}
+
+BcFramePtrs pass_ptrs(bc_ctx* c, BcFramePtrs f, int pass, int width, int height) {
+  f.fin = reinterpret_cast<const BcFrameIn*>(static_cast<char*>(c->dev[1]) + c->off_fin + sizeof(BcFrameIn) * pass);
+  f.width = width;
+  f.height = height;
+  return f;
+}
+
+struct CnnLayout {
+  size_t w, m, v, g;                 // FP32 parameter vectors
+  size_t f1, f2, f3, b3, b2;         // packed fragments: forward 1..3, backward-data 3 and 2
+  size_t a1, a2, gy, gz2, gz1;       // BF16 NHWC activations / gradients
+  size_t part, loss;                 // per-tile partial sums
+  size_t coarse, val;                // learned frames: coarse render, validation tiles
+  size_t total;
+  int64_t tiles;
+};
+
+// fragment bytes: ks * nt * 64 lanes * 8 BF16
+constexpr size_t frag_bytes(int ks, int nt) { return (size_t)ks * nt * 64 * 8 * 2; }
+constexpr int kPartWidth = 32 * 288 + 32;   // widest per-tile partial (layer 2)
+
+CnnLayout cnn_layout(int n, int h, int w) {
+  CnnLayout L;
+  size_t m = 0;
+  auto take = [&](size_t bytes) { size_t o = m; m = align256(m + bytes); return o; };
+  L.w = take(4 * CNN_N_PARAMS);
+  L.m = take(4 * CNN_N_PARAMS);
+  L.v = take(4 * CNN_N_PARAMS);
+  L.g = take(4 * CNN_N_PARAMS);
+  L.f1 = take(frag_bytes(2, 2));
+  L.f2 = take(frag_bytes(9, 2));
+  L.f3 = take(frag_bytes(9, 1));
+  L.b3 = take(frag_bytes(5, 2));
+  L.b2 = take(frag_bytes(9, 2));
+  const size_t px = (size_t)n * h * w;
+  L.a1 = take(px * 32 * 2);
+  L.a2 = take(px * 32 * 2);
+  L.gy = take(px * 16 * 2);
+  L.gz2 = take(px * 32 * 2);
+  L.gz1 = take(px * 32 * 2);
+  L.tiles = (int64_t)n * ((h + 15) / 16) * ((w + 15) / 16);
+  L.part = take((size_t)L.tiles * kPartWidth * 4);
+  L.loss = take((size_t)L.tiles * 4);
+  L.coarse = take(px * 16);
+  L.val = take(px * 4 * 16);
+  L.total = m;
+  return L;
+}
+
+int cnn_infer(bc_ctx* c, const CnnLayout& L, const float* coarse, float* fine, int n, int h, int w, hipStream_t st);
+
 }  // namespace
 
 extern "C" {
@@ -254,7 +353,8 @@ int bc_create(int hip_device, bc_ctx** out) {
     c->render_workgroups = c->n_cu * 8;
     bool ok = true;
     for (int i = 0; i < 2 && ok; ++i) {
-      ok = hipHostMalloc(reinterpret_cast<void**>(&c->pinned[i]), sizeof(BcFrameIn), hipHostMallocDefault) == hipSuccess;
+      ok = hipHostMalloc(reinterpret_cast<void**>(&c->pinned[i]), sizeof(BcFrameIn) * kPasses, hipHostMallocDefault) ==
+           hipSuccess;
       ok = ok && hipEventCreateWithFlags(&c->copy_done[i], hipEventDisableTiming) == hipSuccess;
     }
     ok = ok && hipEventCreateWithFlags(&c->frame_done, hipEventDisableTiming) == hipSuccess;
@@ -356,13 +456,19 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
         max_region = std::max(max_region, (size_t)region);
       }
   const int64_t tiles_frame = (int64_t)((max_w + BC_TILE - 1) / BC_TILE) * ((max_h + BC_TILE - 1) / BC_TILE);
-  if (max_tiles == 0)
-    max_tiles = (int64_t)max_views * tiles_frame * std::min<int64_t>(nbt, 2 * ((int64_t)nb[0] + nb[1] + nb[2]) + 4);
+  if (max_tiles == 0) {
+    // every brick over the whole frame when that is small, else a bound on how
+    // many brick rectangles overlap a screen tile
+    const int64_t full = (int64_t)max_views * tiles_frame * nbt;
+    max_tiles = full <= (int64_t(1) << 18)
+                    ? full
+                    : (int64_t)max_views * tiles_frame * std::min<int64_t>(nbt, 2 * ((int64_t)nb[0] + nb[1] + nb[2]) + 4);
+  }
   c->max_tiles = max_tiles;
   c->bytes[0] = align256((size_t)off * c->elem_bytes);
   size_t m = 0;
   c->off_bricks = m; m = align256(m + sizeof(BcBrick) * c->n_bricks);
-  c->off_fin = m; m = align256(m + sizeof(BcFrameIn));
+  c->off_fin = m; m = align256(m + sizeof(BcFrameIn) * kPasses);
   c->off_views = m; m = align256(m + sizeof(BcViewParams) * BC_MAX_VIEWS);
   c->off_order = m; m = align256(m + sizeof(int32_t) * BC_MAX_VIEWS * c->n_bricks);
   c->off_rects = m; m = align256(m + sizeof(int32_t) * 4 * BC_MAX_VIEWS * c->n_bricks);
@@ -547,52 +653,58 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
   if (!c->has_view) return fail(c, BC_E_STATE, "bc_render_frame: no view");
   if (!out) return fail(c, BC_E_ARG, "bc_render_frame: out is NULL");
   if (reinterpret_cast<uintptr_t>(out) & 15) return fail(c, BC_E_ARG, "bc_render_frame: out not 16-byte aligned");
+  const int n = (int)c->views.size();
+  const int W = c->views[0].width, H = c->views[0].height;
+  if (c->learned) {
+    if (!c->cnn_bound || !c->cnn_has_w)
+      return fail(c, BC_E_STATE, "bc_render_frame: learned frames need the upsampler workspace and weights");
+    if ((W & 1) || (H & 1)) return fail(c, BC_E_ARG, "bc_render_frame: learned frames need an even width and height");
+    if (n > c->cnn_max_n || W / 2 > c->cnn_max_w || H / 2 > c->cnn_max_h)
+      return fail(c, BC_E_ARG, "bc_render_frame: %d views of %d x %d exceed the upsampler plan", n, W, H);
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIPCHECK(c, hipSetDevice(c->device));
   const int slot = c->ring;
   c->ring ^= 1;
   if (c->copy_pending[slot]) HIPCHECK(c, hipEventSynchronize(c->copy_done[slot]));
-  BcFrameIn* fin = c->pinned[slot];
-  const int n = (int)c->views.size();
-  for (int i = 0; i < n; ++i) {
-    BcViewIn& vi = fin->views[i];
-    std::memcpy(vi.mv, c->views[i].modelview, sizeof vi.mv);
-    std::memcpy(vi.pr, c->views[i].projection, sizeof vi.pr);
-    vi.width = c->views[i].width;
-    vi.height = c->views[i].height;
-    vi.step = c->views[i].step;
-    vi.tau = c->views[i].ert_threshold;
-  }
-  fin->n_views = n;
-  fin->K = c->K;
-  const double dt = c->views[0].step;
-  const double scale = (c->K - 1) / (c->vmax - c->vmin);
-  fin->tf_scale = (float)scale;
-  fin->tf_bias = (float)(-c->vmin * scale);
-  for (int k = 0; k < c->K; ++k) {
-    const double a = c->tf[4 * k + 3];
-    const double ac = 1.0 - std::pow(1.0 - a, dt / c->dt_ref);
-    fin->table[k][0] = (float)(ac * c->tf[4 * k + 0]);
-    fin->table[k][1] = (float)(ac * c->tf[4 * k + 1]);
-    fin->table[k][2] = (float)(ac * c->tf[4 * k + 2]);
-    fin->table[k][3] = (float)ac;
-  }
-  const size_t bytes = offsetof(BcFrameIn, table) + sizeof(float) * 4 * c->K;
+  BcFrameIn* pins = c->pinned[slot];
   char* meta = static_cast<char*>(c->dev[1]);
-  HIPCHECK(c, hipMemcpyAsync(meta + c->off_fin, fin, bytes, hipMemcpyHostToDevice, st));
+  const int passes = c->learned ? kPasses : 1;
+  const double dt = c->views[0].step;
+  ++c->frame_counter;
+  for (int ps = 0; ps < passes; ++ps) {
+    const bool coarse = c->learned && ps == 0;
+    PassSpec spec;
+    spec.width = coarse ? W / 2 : W;
+    spec.height = coarse ? H / 2 : H;
+    spec.step = coarse ? c->coarse_step : dt;
+    spec.stride = (c->learned && ps == 1) ? c->val_stride : 1;
+    // validation tiles move from frame to frame (stratified: one per stride x stride block)
+    const uint64_t h = c->frame_counter * 0x9E3779B97F4A7C15ull;
+    spec.ox = spec.stride > 1 ? (int)((h >> 32) % (uint64_t)spec.stride) : 0;
+    spec.oy = spec.stride > 1 ? (int)((h >> 16) % (uint64_t)spec.stride) : 0;
+    spec.reset = ps == 0;
+    spec.conditional = c->learned && ps == 2;
+    fill_pass(c, pins + ps, spec);
+    const size_t bytes = offsetof(BcFrameIn, table) + sizeof(float) * 4 * c->K;
+    HIPCHECK(c, hipMemcpyAsync(meta + c->off_fin + sizeof(BcFrameIn) * ps, pins + ps, bytes, hipMemcpyHostToDevice,
+                               st));
+  }
   HIPCHECK(c, hipEventRecord(c->copy_done[slot], st));
   c->copy_pending[slot] = true;
   c->frame_views = n;
-  BcFramePtrs f = frame_ptrs(c);
-  // empty-space classification depends on the corrected table only: redo it
-  // when the table differs from the one last classified
+  // empty-space classification depends only on which table entries are zero
+  // (and on the value-to-table mapping): redo it when that pattern changes
   bool classify = false;
   if (c->ess) {
-    const float* tab = &fin->table[0][0];
-    classify = !c->occ_valid || c->occ_table.size() != (size_t)(4 * c->K) ||
-               std::memcmp(c->occ_table.data(), tab, sizeof(float) * 4 * c->K) != 0;
+    std::vector<float> key(c->K + 3);
+    key[0] = (float)c->K;
+    key[1] = pins[0].tf_scale;
+    key[2] = pins[0].tf_bias;
+    for (int k = 0; k < c->K; ++k) key[3 + k] = pins[0].table[k][3] != 0.0f ? 1.0f : 0.0f;
+    classify = !c->occ_valid || c->occ_table != key;
     if (classify) {
-      c->occ_table.assign(tab, tab + 4 * c->K);
+      c->occ_table = key;
       c->occ_valid = true;
     }
   }
@@ -607,16 +719,55 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     ev = &c->tev[4 * (size_t)c->timed_frames];
     ++c->timed_frames;
   }
+  BcFramePtrs f = frame_ptrs(c);
   if (classify) HIPCHECK(c, bc_launch_classify(f, c->max_occ_words, st));
   if (ev) HIPCHECK(c, hipEventRecord(ev[0], st));
-  HIPCHECK(c, bc_launch_setup(f, st));
-  if (ev) HIPCHECK(c, hipEventRecord(ev[1], st));
-  HIPCHECK(c, bc_launch_render(f, c->render_workgroups, st));
-  if (ev) HIPCHECK(c, hipEventRecord(ev[2], st));
-  HIPCHECK(c, bc_launch_composite(f, reinterpret_cast<float4*>(out), st));
+  if (!c->learned) {
+    HIPCHECK(c, bc_launch_setup(f, st));
+    if (ev) HIPCHECK(c, hipEventRecord(ev[1], st));
+    HIPCHECK(c, bc_launch_render(f, c->render_workgroups, st));
+    if (ev) HIPCHECK(c, hipEventRecord(ev[2], st));
+    HIPCHECK(c, bc_launch_composite(f, reinterpret_cast<float4*>(out), st));
+  } else {
+    const CnnLayout L = cnn_layout(c->cnn_max_n, c->cnn_max_h, c->cnn_max_w);
+    float* coarse_img = reinterpret_cast<float*>(c->cnn_ws + L.coarse);
+    float* val_img = reinterpret_cast<float*>(c->cnn_ws + L.val);
+    BcFramePtrs fc = pass_ptrs(c, f, 0, W / 2, H / 2);
+    HIPCHECK(c, bc_launch_setup(fc, st));
+    HIPCHECK(c, bc_launch_render(fc, c->render_workgroups, st));
+    HIPCHECK(c, bc_launch_composite(fc, reinterpret_cast<float4*>(coarse_img), st));
+    if (ev) HIPCHECK(c, hipEventRecord(ev[1], st));
+    int r = cnn_infer(c, L, coarse_img, out, n, H / 2, W / 2, st);
+    if (r) return r;
+    if (ev) HIPCHECK(c, hipEventRecord(ev[2], st));
+    BcFramePtrs fv = pass_ptrs(c, f, 1, W, H);
+    HIPCHECK(c, bc_launch_setup(fv, st));
+    HIPCHECK(c, bc_launch_render(fv, c->render_workgroups, st));
+    HIPCHECK(c, bc_launch_composite(fv, reinterpret_cast<float4*>(val_img), st));
+    HIPCHECK(c, bc_launch_psnr(fv, reinterpret_cast<const float4*>(val_img), reinterpret_cast<const float4*>(out), st));
+    BcFramePtrs fp = pass_ptrs(c, f, 2, W, H);
+    HIPCHECK(c, bc_launch_setup(fp, st));
+    HIPCHECK(c, bc_launch_render(fp, c->render_workgroups, st));
+    HIPCHECK(c, bc_launch_composite(fp, reinterpret_cast<float4*>(out), st));
+  }
   if (ev) HIPCHECK(c, hipEventRecord(ev[3], st));
   HIPCHECK(c, hipEventRecord(c->frame_done, st));
   c->frame_pending = true;
+  c->last_learned = c->learned;
+  return BC_OK;
+}
+
+int bc_set_learned(bc_ctx* c, int enable, double coarse_step, double psnr_threshold_db, int validate_stride) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (enable != 0 && enable != 1) return fail(c, BC_E_ARG, "bc_set_learned: enable must be 0 or 1");
+  if (!(std::isfinite(coarse_step) && coarse_step > 0.0)) return fail(c, BC_E_ARG, "bc_set_learned: coarse_step must be > 0");
+  if (!std::isfinite(psnr_threshold_db)) return fail(c, BC_E_ARG, "bc_set_learned: threshold must be finite");
+  if (validate_stride < 1 || validate_stride > 64) return fail(c, BC_E_ARG, "bc_set_learned: validate_stride outside [1, 64]");
+  c->learned = enable != 0;
+  c->coarse_step = coarse_step;
+  c->psnr_threshold = psnr_threshold_db;
+  c->val_stride = validate_stride;
   return BC_OK;
 }
 
@@ -633,7 +784,9 @@ int bc_get_frame_stats(bc_ctx* c, bc_frame_stats* s) {
   HIPCHECK(c, hipMemcpy(&h, meta + c->off_ctr, offsetof(BcCounters, minmax), hipMemcpyDeviceToHost));
   s->nominal_samples = h.nominal;
   s->evaluated_samples = h.evaluated;
-  s->n_tiles = h.n_items;
+  s->n_tiles = h.total_items;
+  s->fell_back = c->last_learned ? (int32_t)h.fallback : -1;
+  s->psnr_db = c->last_learned ? h.psnr_db : NAN;
   s->reserved = 0;
   return BC_OK;
 }
@@ -768,45 +921,6 @@ int bc_read_brick(bc_ctx* c, int b, void* dst, size_t cap, int32_t dims[3]) {
 // ======================================================================
 namespace {
 
-struct CnnLayout {
-  size_t w, m, v, g;                 // FP32 parameter vectors
-  size_t f1, f2, f3, b3, b2;         // packed fragments: forward 1..3, backward-data 3 and 2
-  size_t a1, a2, gy, gz2, gz1;       // BF16 NHWC activations / gradients
-  size_t part, loss;                 // per-tile partial sums
-  size_t total;
-  int64_t tiles;
-};
-
-// fragment bytes: ks * nt * 64 lanes * 8 BF16
-constexpr size_t frag_bytes(int ks, int nt) { return (size_t)ks * nt * 64 * 8 * 2; }
-constexpr int kPartWidth = 32 * 288 + 32;   // widest per-tile partial (layer 2)
-
-CnnLayout cnn_layout(int n, int h, int w) {
-  CnnLayout L;
-  size_t m = 0;
-  auto take = [&](size_t bytes) { size_t o = m; m = align256(m + bytes); return o; };
-  L.w = take(4 * CNN_N_PARAMS);
-  L.m = take(4 * CNN_N_PARAMS);
-  L.v = take(4 * CNN_N_PARAMS);
-  L.g = take(4 * CNN_N_PARAMS);
-  L.f1 = take(frag_bytes(2, 2));
-  L.f2 = take(frag_bytes(9, 2));
-  L.f3 = take(frag_bytes(9, 1));
-  L.b3 = take(frag_bytes(5, 2));
-  L.b2 = take(frag_bytes(9, 2));
-  const size_t px = (size_t)n * h * w;
-  L.a1 = take(px * 32 * 2);
-  L.a2 = take(px * 32 * 2);
-  L.gy = take(px * 16 * 2);
-  L.gz2 = take(px * 32 * 2);
-  L.gz1 = take(px * 32 * 2);
-  L.tiles = (int64_t)n * ((h + 15) / 16) * ((w + 15) / 16);
-  L.part = take((size_t)L.tiles * kPartWidth * 4);
-  L.loss = take((size_t)L.tiles * 4);
-  L.total = m;
-  return L;
-}
-
 CnnPackTable cnn_pack_table(bc_ctx* c, const CnnLayout& L) {
   CnnPackTable t;
   auto ent = [&](size_t off, int w_off, int cin, int cout, int ks, int nt, int tr) {
@@ -872,6 +986,20 @@ int cnn_gradients(bc_ctx* c, const float* coarse, const float* target, int n, in
     const int nw = j.cout * j.cin * 9;
     HIPCHECK(c, cnn_launch_reduce(F32(L.part), L.tiles, nw + j.cout, g + j.w_off, g + j.b_off, nw, st));
   }
+  return BC_OK;
+}
+
+int cnn_infer(bc_ctx* c, const CnnLayout& L, const float* coarse, float* fine, int n, int h, int w, hipStream_t st) {
+  CnnInferArgs a;
+  a.x = coarse;
+  a.out = fine;
+  a.params = reinterpret_cast<const float*>(c->cnn_ws + L.w);
+  a.wf1 = reinterpret_cast<const uint4*>(c->cnn_ws + L.f1);
+  a.wf2 = reinterpret_cast<const uint4*>(c->cnn_ws + L.f2);
+  a.wf3 = reinterpret_cast<const uint4*>(c->cnn_ws + L.f3);
+  a.h = h;
+  a.w = w;
+  HIPCHECK(c, cnn_launch_infer(a, n, st));
   return BC_OK;
 }
 
@@ -977,15 +1105,7 @@ int bc_cnn_forward(bc_ctx* c, const float* coarse, float* fine, int n, int h, in
   if (r) return r;
   HIPCHECK(c, hipSetDevice(c->device));
   const CnnLayout L = cnn_layout(c->cnn_max_n, c->cnn_max_h, c->cnn_max_w);
-  CnnInferArgs a;
-  a.x = coarse; a.out = fine;
-  a.params = reinterpret_cast<const float*>(c->cnn_ws + L.w);
-  a.wf1 = reinterpret_cast<const uint4*>(c->cnn_ws + L.f1);
-  a.wf2 = reinterpret_cast<const uint4*>(c->cnn_ws + L.f2);
-  a.wf3 = reinterpret_cast<const uint4*>(c->cnn_ws + L.f3);
-  a.h = h; a.w = w;
-  HIPCHECK(c, cnn_launch_infer(a, n, static_cast<hipStream_t>(stream)));
-  return BC_OK;
+  return cnn_infer(c, L, coarse, fine, n, h, w, static_cast<hipStream_t>(stream));
 }
 
 int bc_cnn_gradients(bc_ctx* c, const float* coarse, const float* target, int n, int h, int w, float* grad,

@@ -231,14 +231,17 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
     for (int b = tid; b < nb; b += blockDim.x) brick_rect(vp, f.bricks[b], f.rects + ((int64_t)v * nb + b) * 4);
     __syncthreads();
   }
-  // work items, brick-major: entry k = b * nv + v owns the tiles of its rectangle
+  // work items, brick-major: entry k = b * nv + v owns the selected tiles of
+  // its rectangle; a conditional pass without the fall-back flag has none
+  const bool skip = f.fin->conditional && !f.ctr->fallback;
+  const int ts = f.fin->tile_stride, tox = f.fin->tile_ox, toy = f.fin->tile_oy;
   const int K = nb * nv;
   const int seg = (K + blockDim.x - 1) / blockDim.x;
   const int k0 = tid * seg, k1 = min(k0 + seg, K);
   int32_t sum = 0;
   for (int k = k0; k < k1; ++k) {
     const int32_t* r = f.rects + ((int64_t)(k % nv) * nb + k / nv) * 4;
-    sum += (r[2] - r[0]) * (r[3] - r[1]);
+    sum += skip ? 0 : sel_count(r[0], r[2], ts, tox) * sel_count(r[1], r[3], ts, toy);
   }
   spart[tid] = sum;
   __syncthreads();
@@ -250,23 +253,32 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
       run += t;
     }
     f.item_base[K] = run;
-    f.ctr->n_items = (uint32_t)min((int64_t)run, f.max_items);
+    const uint32_t n_items = (uint32_t)min((int64_t)run, f.max_items);
+    f.ctr->n_items = n_items;
     f.ctr->queue = 0u;
-    f.ctr->nominal = 0ull;
-    f.ctr->evaluated = 0ull;
+    if (f.fin->reset_counters) {
+      f.ctr->nominal = 0ull;
+      f.ctr->evaluated = 0ull;
+      f.ctr->total_items = n_items;
+    } else {
+      f.ctr->total_items += n_items;
+    }
   }
   __syncthreads();
   int32_t run = spart[tid];
   for (int k = k0; k < k1; ++k) {
     f.item_base[k] = run;
     const int32_t* r = f.rects + ((int64_t)(k % nv) * nb + k / nv) * 4;
-    run += (r[2] - r[0]) * (r[3] - r[1]);
+    run += skip ? 0 : sel_count(r[0], r[2], ts, tox) * sel_count(r[1], r[3], ts, toy);
   }
 }
 
 __global__ __launch_bounds__(64) void composite_kernel(BcFramePtrs f, float4* __restrict__ out) {
+  if (f.fin->conditional && !f.ctr->fallback) return;
   const int v = blockIdx.z;
   const int tx = blockIdx.x, ty = blockIdx.y;
+  const int ts = f.fin->tile_stride, tox = f.fin->tile_ox, toy = f.fin->tile_oy;
+  if (tx % ts != tox || ty % ts != toy) return;
   const int lane = threadIdx.x;
   const int nb = f.n_bricks, nv = f.n_views;
   const int W = f.width, H = f.height;
@@ -277,7 +289,9 @@ __global__ __launch_bounds__(64) void composite_kernel(BcFramePtrs f, float4* __
     const int b = f.order[v * nb + k];
     const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
     if (tx < r[0] || tx >= r[2] || ty < r[1] || ty >= r[3]) continue;
-    const int64_t item = (int64_t)f.item_base[b * nv + v] + (int64_t)(ty - r[1]) * (r[2] - r[0]) + (tx - r[0]);
+    const int fx = sel_first(r[0], ts, tox), fy = sel_first(r[1], ts, toy);
+    const int cx = sel_count(r[0], r[2], ts, tox);
+    const int64_t item = (int64_t)f.item_base[b * nv + v] + (int64_t)((ty - fy) / ts) * cx + (tx - fx) / ts;
     if (item >= (int64_t)f.max_items) continue;
     const float4 S = f.sub[item * 64 + lane];
     const float om = 1.0f - F.w;
@@ -289,10 +303,64 @@ __global__ __launch_bounds__(64) void composite_kernel(BcFramePtrs f, float4* __
   if (px < W && py < H) out[((int64_t)v * H + py) * W + px] = F;
 }
 
+// Learned frame: PSNR (peak 1) of the upsampled image against the plain
+// render over the validation tiles, and the fall-back decision.
+__global__ __launch_bounds__(1024) void psnr_kernel(BcFramePtrs f, const float4* __restrict__ ref,
+                                                    const float4* __restrict__ img) {
+  __shared__ double red[1024];
+  const int ts = f.fin->tile_stride, tox = f.fin->tile_ox, toy = f.fin->tile_oy;
+  const int W = f.width, H = f.height, nv = f.n_views;
+  const int tiles_x = (W + BC_TILE - 1) / BC_TILE, tiles_y = (H + BC_TILE - 1) / BC_TILE;
+  const int sx = sel_count(0, tiles_x, ts, tox), sy = sel_count(0, tiles_y, ts, toy);
+  const int fx = sel_first(0, ts, tox), fy = sel_first(0, ts, toy);
+  const int64_t total = (int64_t)nv * sx * sy * 64;
+  double acc = 0.0;
+  double cnt = 0.0;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int lane = (int)(e & 63);
+    const int64_t t = e >> 6;
+    const int v = (int)(t / ((int64_t)sx * sy));
+    const int rem = (int)(t % ((int64_t)sx * sy));
+    const int tx = fx + (rem % sx) * ts, ty = fy + (rem / sx) * ts;
+    const int px = tx * BC_TILE + (lane & (BC_TILE - 1)), py = ty * BC_TILE + (lane / BC_TILE);
+    if (px >= W || py >= H) continue;
+    const int64_t i = ((int64_t)v * H + py) * W + px;
+    const float4 a = ref[i], b = img[i];
+    const double dx = (double)a.x - b.x, dy = (double)a.y - b.y, dz = (double)a.z - b.z, dw = (double)a.w - b.w;
+    acc += dx * dx + dy * dy + dz * dz + dw * dw;
+    cnt += 4.0;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double sum = red[0];
+  __syncthreads();
+  red[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mse = red[0] > 0.0 ? sum / red[0] : 0.0;
+    const float p = mse > 0.0 ? (float)(10.0 * log10(1.0 / mse)) : INFINITY;
+    f.ctr->psnr_db = p;
+    f.ctr->fallback = (p < f.fin->psnr_threshold) ? 1u : 0u;
+  }
+}
+
 }  // namespace
 
 hipError_t bc_launch_setup(const BcFramePtrs& f, hipStream_t st) {
   setup_kernel<<<1, 1024, 0, st>>>(f);
+  return hipGetLastError();
+}
+
+hipError_t bc_launch_psnr(const BcFramePtrs& f, const float4* ref, const float4* img, hipStream_t st) {
+  psnr_kernel<<<1, 1024, 0, st>>>(f, ref, img);
   return hipGetLastError();
 }
 

@@ -44,3 +44,11 @@ hipError_t bc_launch_setup(const BcFramePtrs& f, hipStream_t st);
 hipError_t bc_launch_classify(const BcFramePtrs& f, int max_words, hipStream_t st);
 hipError_t bc_launch_render(const BcFramePtrs& f, int n_workgroups, hipStream_t st);
 hipError_t bc_launch_composite(const BcFramePtrs& f, float4* out, hipStream_t st);
+hipError_t bc_launch_psnr(const BcFramePtrs& f, const float4* ref, const float4* img, hipStream_t st);
+
+// tile selection {t : t % s == o}: first selected tile >= lo, count in [lo, hi)
+__device__ __forceinline__ int sel_first(int lo, int s, int o) { return lo + ((o - lo) % s + s) % s; }
+__device__ __forceinline__ int sel_count(int lo, int hi, int s, int o) {
+  const int f = sel_first(lo, s, o);
+  return f < hi ? (hi - 1 - f) / s + 1 : 0;
+}

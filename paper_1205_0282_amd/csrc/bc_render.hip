@@ -259,6 +259,7 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
   const int KB = nb * nv;
   const uint32_t n_items = f.ctr->n_items;
   const bool ess = f.ess != 0;
+  const int ts = fin->tile_stride, tox = fin->tile_ox, toy = fin->tile_oy;
   uint64_t nominal = 0, evaluated = 0;
   for (;;) {
     uint32_t item = 0;
@@ -272,9 +273,9 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
     }
     const int b = lo / nv, v = lo % nv;
     const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
-    const int tw = r[2] - r[0];
+    const int cx = sel_count(r[0], r[2], ts, tox);
     const int local = (int)(item - (uint32_t)f.item_base[lo]);
-    const int tx = r[0] + local % tw, ty = r[1] + local / tw;
+    const int tx = sel_first(r[0], ts, tox) + (local % cx) * ts, ty = sel_first(r[1], ts, toy) + (local / cx) * ts;
     const int px = tx * BC_TILE + (lane & (BC_TILE - 1));
     const int py = ty * BC_TILE + (lane / BC_TILE);
     const BcViewParams& vp = f.views[v];

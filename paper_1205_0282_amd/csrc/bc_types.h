@@ -17,11 +17,19 @@ struct BcViewIn {
   double step, tau;
 };
 
-// Per-frame input copied host -> device in one transfer before the frame.
+// Per-pass input copied host -> device before the frame.  A plain frame is one
+// pass; a learned frame is three (coarse render, sparse validation render,
+// conditional full render).
 struct BcFrameIn {
   BcViewIn views[BC_MAX_VIEWS];
   int32_t n_views, K;
   float tf_scale, tf_bias;   // table coordinate x = v * tf_scale + tf_bias
+  int32_t tile_stride;       // 1: every screen tile; s > 1: tiles with tx % s == ox and ty % s == oy
+  int32_t tile_ox, tile_oy;
+  int32_t reset_counters;    // the pass starts the frame's sample counters
+  int32_t conditional;       // the pass runs only if the validation set the fall-back flag
+  float psnr_threshold;      // validation pass: dB below which the frame falls back
+  int32_t pad_[2];
   float table[BC_MAX_K][4];  // opacity-corrected premultiplied RGBA entries (only K used)
 };
 
@@ -60,9 +68,13 @@ struct BcBrick {
 };
 
 struct BcCounters {
-  uint32_t n_items;          // work items of the frame
+  uint32_t n_items;          // work items of the pass
   uint32_t queue;            // next work item (persistent kernel)
   unsigned long long nominal;
   unsigned long long evaluated;
+  uint32_t fallback;         // learned frame: validation PSNR below threshold
+  float psnr_db;             // learned frame: PSNR of the validation tiles
+  uint32_t total_items;      // work items of all passes of the frame
+  uint32_t pad_;
   uint32_t minmax[BC_MAX_BRICKS][2];   // load time: ordered-int min/max per brick
 };

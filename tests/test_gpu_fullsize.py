@@ -1,0 +1,47 @@
+"""Parity at the benchmark's full size: the 1024^3 FP32 cube (4x4x4 bricks of
+256^3), perspective 1920x1080, step 0.5, termination at 0.99, rendered by the
+same launch configuration bench.py times, against the FP64 oracle at sampled
+pixels (each computed one by one by the oracle)."""
+import numpy as np
+import pytest
+
+from oracle import raycast as rc
+from paper_1205_0282_amd import binding, synth
+
+from gpu_util import TOL, cam_of
+
+pytestmark = pytest.mark.gpu
+
+
+def test_cube1024_frame_sampled_pixels():
+    import torch
+    recipe = synth.RECIPE_1024
+    vol = synth.make_cube(recipe, workers=16)
+    vmin, vmax = float(vol.min()), float(vol.max())
+    rgba = synth.ramp_tf(vmin, vmax)
+    dims = recipe.dims
+    bc = binding.BrickCaster(0)
+    bc.plan(dims, (256, 256, 256), storage="f32", max_views=1, max_w=1920, max_h=1080)
+    bc.bind()
+    src = torch.from_numpy(vol).cuda()
+    bc.load(src)
+    del src
+    bc.set_transfer_function(rgba, vmin, vmax)
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (256, 256, 256)))
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    for frame in (0, 23):
+        v = synth.orbit_view(dims, frame)
+        bc.set_views([v])
+        img = bc.render()[0].cpu().numpy().astype(np.float64)
+        cam = cam_of(v)
+        rng = np.random.default_rng(100 + frame)
+        cand = np.stack([rng.integers(0, 1920, 2000), rng.integers(0, 1080, 2000)], axis=1)
+        o, d = cam.rays(cand[:, 0], cand[:, 1])
+        _, _, hit = rc.global_interval(o, d, dims)
+        pix = np.concatenate([cand[hit][:96], cand[~hit][:16]])
+        res = rc.render_bricked(stored, dims, cam, tf, 0.5, 0.99, pixels=pix)
+        err = rc.max_abs_with_branches(img[pix[:, 1], pix[:, 0]], res)
+        print(f"frame {frame}: max err {err.max():.3g} over {len(pix)} pixels, {int(res.tie.sum())} near-tie rays")
+        assert err[~res.overflow].max() <= TOL
+        assert res.image[:, 3].max() > 0.1
+    bc.close()
