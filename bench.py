@@ -24,6 +24,7 @@ processes forked over the host cores before the GPU is touched.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import multiprocessing as mp
@@ -67,6 +68,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target wall time of the oracle sample (0 disables the CPU baseline)")
     p.add_argument("--cpu-workers", type=int, default=0, help="0 = all host cores, at most 16")
+    p.add_argument("--learned", action="store_true",
+                   help="time learned frames: coarse render + trained upsampler, validated against plain tiles")
+    p.add_argument("--weights", default=os.path.join(ROOT, "paper_1205_0282_amd", "weights", "upsampler.npy"))
+    p.add_argument("--psnr-threshold", type=float, default=40.0)
     p.add_argument("--frames", type=int, default=ORBIT,
                    help="distinct orbit frames cycled through (the first N of the 64-frame orbit)")
     p.add_argument("--check-pixels", type=int, default=1024,
@@ -163,6 +168,49 @@ def cpu_baseline(vol, recipe, brick, view, rgba, vmin, vmax, seconds, workers):
                       f"near-tie branches, {samples} samples in {wall:.1f} s over {workers} forked processes"}
 
 
+# ------------------------------------------------------------------ learned frames
+def setup_learned(bc, args, views, out, W, H):
+    """Loads the trained upsampler, measures its quality on every orbit frame
+    against the plain render (untimed) and switches the context to learned
+    frames.  Returns the quality summary."""
+    import torch
+    import torch.nn.functional as F
+    w = np.load(args.weights, allow_pickle=False).astype(np.float32)
+    bc.cnn_setup(1, H // 2, W // 2)
+    bc.cnn_set_weights(w)
+    plain, psnr_net, psnr_bil, psnr_val, fell = [], [], [], [], 0
+    for v in views:
+        bc.set_learned(False)
+        bc.set_views([v])
+        ref = bc.render(out).clone()
+        bc.set_learned(True, 2.0, args.psnr_threshold, 8)
+        img = bc.render(out).clone()
+        st = bc.stats()
+        fell += int(st["fell_back"] == 1)
+        psnr_val.append(st["psnr_db"])
+        # the network alone and the bilinear baseline, from the same coarse render
+        cv = dataclasses.replace(v, width=W // 2, height=H // 2, step=2.0)
+        bc.set_learned(False)
+        bc.set_views([cv])
+        coarse = bc.render(torch.empty((1, H // 2, W // 2, 4), dtype=torch.float32, device=out.device)).clone()
+        net = bc.cnn_forward(coarse)
+        bil = F.interpolate(coarse.permute(0, 3, 1, 2), scale_factor=2, mode="bilinear",
+                            align_corners=False).permute(0, 2, 3, 1)
+        for lst, a in ((psnr_net, net), (psnr_bil, bil)):
+            mse = float(((a - ref) ** 2).mean())
+            lst.append(float("inf") if mse == 0 else 10 * math.log10(1.0 / mse))
+        del img
+    bc.set_learned(True, 2.0, args.psnr_threshold, 8)
+    summary = {"weights": os.path.relpath(args.weights, ROOT), "coarse": [W // 2, H // 2], "coarse_step": 2.0,
+               "psnr_threshold_db": args.psnr_threshold, "validate_stride": 8,
+               "psnr_network_vs_plain_db": {"mean": float(np.mean(psnr_net)), "min": float(np.min(psnr_net))},
+               "psnr_bilinear_vs_plain_db": {"mean": float(np.mean(psnr_bil)), "min": float(np.min(psnr_bil))},
+               "psnr_validation_db_mean": float(np.mean(psnr_val)), "fell_back_frames": fell,
+               "frames": len(views)}
+    log(f"learned: {summary}")
+    return summary
+
+
 # ------------------------------------------------------------------ GPU
 def main():
     args = parse()
@@ -233,6 +281,10 @@ def main():
         precision = precision_report(img[pix[:, 1], pix[:, 0]], ref_img, branches)
         log(f"precision vs FP64 oracle: {precision}")
 
+    learned = None
+    if args.learned:
+        learned = setup_learned(bc, args, views, out, W, H)
+
     for i in range(args.warmup):
         bc.set_views([views[i % nf]])
         bc.render(out)
@@ -257,7 +309,7 @@ def main():
     ms_step = elapsed / args.steps * 1e3
     result = {
         "metric": "Gsamples/s + fps @1920x1080 on 1024^3 cube",
-        "value": tot_samples / elapsed / 1e9,
+        "value": tot_samples / elapsed / 1e9,   # learned frames: nominal samples of the plain frame (equivalent)
         "unit": "Gsamples/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -281,6 +333,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "render_kernel", "algo_bytes_per_launch": tot_bytes / args.steps},
         "precision_vs_oracle": precision,
+        "learned": learned,
         "cpu_baseline": cpu,
     }
     bc.close()

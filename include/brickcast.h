@@ -183,8 +183,11 @@ int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);
  *    the opacity-corrected table changes.
  *  BC_OPT_RENDER_WORKGROUPS: workgroups (256 threads) of the persistent
  *    ray-casting launch; default 8 per compute unit.
+ *  BC_OPT_SAMPLE_CHUNK (32 or 64, default 64): samples per ray whose
+ *    occupancy is gathered before the occupied ones are evaluated.  Images do
+ *    not depend on it.
  * Errors: BC_E_ARG for an unknown option or a value out of range. */
-enum bc_option { BC_OPT_EMPTY_SKIP = 0, BC_OPT_RENDER_WORKGROUPS = 1 };
+enum bc_option { BC_OPT_EMPTY_SKIP = 0, BC_OPT_RENDER_WORKGROUPS = 1, BC_OPT_SAMPLE_CHUNK = 2 };
 int bc_set_option(bc_ctx* ctx, int option, int64_t value);
 
 /* Per-stage GPU time, measured with HIP events recorded on the frame's own

@@ -28,7 +28,7 @@ EXPORTS = [
     "bc_cnn_gradients", "bc_cnn_train_step", "bc_set_learned",
 ]
 CNN_N_PARAMS = 15056
-BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS = 0, 1
+BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS, BC_OPT_SAMPLE_CHUNK = 0, 1, 2
 
 
 class LibraryMissing(RuntimeError):

@@ -65,6 +65,7 @@ struct bc_ctx {
   // kernel launch shape and options
   int render_workgroups = 0;
   bool ess = true;
+  int chunk = 64;
   // cell-occupancy bits are valid for this table (opacity-corrected entries)
   bool occ_valid = false;
   std::vector<float> occ_table;
@@ -214,6 +215,7 @@ BcFramePtrs frame_ptrs(bc_ctx* c) {
   f.pool = c->dev[0];
   f.occ = reinterpret_cast<uint32_t*>(meta + c->off_occ);
   f.ess = c->ess ? 1 : 0;
+  f.chunk = c->chunk;
   f.K = c->K;
   f.n_bricks = c->n_bricks;
   f.n_views = c->frame_views;
@@ -798,6 +800,10 @@ int bc_set_option(bc_ctx* c, int option, int64_t value) {
     case BC_OPT_EMPTY_SKIP:
       if (value != 0 && value != 1) return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_EMPTY_SKIP takes 0 or 1");
       c->ess = value != 0;
+      return BC_OK;
+    case BC_OPT_SAMPLE_CHUNK:
+      if (value != 32 && value != 64) return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_SAMPLE_CHUNK takes 32 or 64");
+      c->chunk = (int)value;
       return BC_OK;
     case BC_OPT_RENDER_WORKGROUPS:
       if (value < 1 || value > (1 << 20))

@@ -32,6 +32,7 @@ struct BcFramePtrs {
   const void* pool;
   uint32_t* occ;          // cell-occupancy bits of every brick
   int32_t ess;            // skip samples in clear cells
+  int32_t chunk;          // samples per occupancy-mask chunk of the ray caster (32 or 64)
   int32_t K;              // transfer-function entries
   int32_t n_bricks, n_views;
   int32_t gdims[3];

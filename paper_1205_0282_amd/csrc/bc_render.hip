@@ -33,15 +33,40 @@
 namespace {
 
 // ------------------------------------------------------------------ storage
+// E4M3 code -> FP32 without branches: the code's exponent and mantissa bits
+// placed at the top of an FP32 mantissa form a number (normal or subnormal) that
+// is 2^-120 times the code's value, so one exact power-of-two product decodes
+// both normal and subnormal codes.
+__device__ __forceinline__ float e4m3_to_f32(uint32_t c) {
+  const float mag = __uint_as_float((c & 0x7fu) << 20) * 1.329227995784916e+36f;   // 2^120
+  return __uint_as_float(__float_as_uint(mag) | ((c & 0x80u) << 24));
+}
+
+template <int FMT>
+__device__ __forceinline__ float decode(uint32_t raw, float s, float o) {
+  if (FMT == 0) return __uint_as_float(raw);
+  if (FMT == 1) return __half2float(__ushort_as_half((unsigned short)raw));
+  return __builtin_fmaf(e4m3_to_f32(raw), s, o);
+}
+
 template <int FMT>
 __device__ __forceinline__ float fetch(const void* __restrict__ pool, uint32_t idx, float s, float o) {
-  if (FMT == 0) return static_cast<const float*>(pool)[idx];
-  if (FMT == 1) return __half2float(static_cast<const __half*>(pool)[idx]);
-  const uint32_t c = static_cast<const uint8_t*>(pool)[idx];
-  const uint32_t e = (c >> 3) & 15u, m = c & 7u;
-  float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
-  mag = (c & 0x80u) ? -mag : mag;
-  return __builtin_fmaf(mag, s, o);
+  if (FMT == 0) return decode<0>(__float_as_uint(static_cast<const float*>(pool)[idx]), s, o);
+  if (FMT == 1) return decode<1>(static_cast<const uint16_t*>(pool)[idx], s, o);
+  return decode<2>(static_cast<const uint8_t*>(pool)[idx], s, o);
+}
+
+// Buffer resources: the hardware range check turns an offset outside the
+// brick (or its occupancy bits) into a zero instead of a fault.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int FMT>
+__device__ __forceinline__ float load_voxel(__amdgpu_buffer_rsrc_t r, uint32_t idx, float s, float o) {
+  if (FMT == 0) return decode<0>(__builtin_amdgcn_raw_buffer_load_b32(r, idx * 4u, 0, 0), s, o);
+  if (FMT == 1) return decode<1>(__builtin_amdgcn_raw_buffer_load_b16(r, idx * 2u, 0, 0), s, o);
+  return decode<2>(__builtin_amdgcn_raw_buffer_load_b8(r, idx, 0, 0), s, o);
 }
 
 // element index, inside the brick, of ghosted local voxel (x, y, z): 4x4x4
@@ -241,7 +266,7 @@ __device__ __forceinline__ int hi32(int64_t v) { return (int)(v >> 32); }
 __device__ __forceinline__ float frac32(int64_t v) { return (float)(uint32_t)v * 2.3283064365386963e-10f; }
 
 // ------------------------------------------------------------------ render
-template <int FMT, bool TF_LDS>
+template <int FMT, bool TF_LDS, int CHUNK>
 __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
   __shared__ float4 s_tab[TF_LDS ? BC_TF_LDS : 1];
   const int lane = threadIdx.x & 63;
@@ -260,6 +285,7 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
   const uint32_t n_items = f.ctr->n_items;
   const bool ess = f.ess != 0;
   const int ts = fin->tile_stride, tox = fin->tile_ox, toy = fin->tile_oy;
+  constexpr uint32_t esz = FMT == 0 ? 4 : (FMT == 1 ? 2 : 1);
   uint64_t nominal = 0, evaluated = 0;
   for (;;) {
     uint32_t item = 0;
@@ -286,37 +312,45 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
       const float tau = vp.tau;
       const int cmx = br.hi[0] - br.lo[0], cmy = br.hi[1] - br.lo[1], cmz = br.hi[2] - br.lo[2];
       const int mbx = br.mb[0], mby = br.mb[1];
-      const int WX = br.occ_w[0], WY = br.occ_w[1];
-      const uint32_t* __restrict__ occ = f.occ + br.occ_offset;
-      const int esz = FMT == 0 ? 4 : (FMT == 1 ? 2 : 1);
-      const void* __restrict__ pool = static_cast<const char*>(f.pool) + br.offset * esz;
+      const uint32_t WX = (uint32_t)br.occ_w[0], WY = (uint32_t)br.occ_w[1];
+      const uint32_t n_occ = WX * WY * (uint32_t)br.occ_w[2];
+      const __amdgpu_buffer_rsrc_t occ = make_rsrc(f.occ + br.occ_offset, n_occ * 4u);
+      const uint32_t n_vox = (uint32_t)br.gdim[0] * (uint32_t)br.gdim[1] * (uint32_t)br.gdim[2];
+      const __amdgpu_buffer_rsrc_t pool = make_rsrc(static_cast<const char*>(f.pool) + br.offset * esz, n_vox * esz);
       const float s_q = br.scale, o_q = br.offs;
       const uint32_t dxb = 61u, dyb = (uint32_t)mbx * 64u - 12u, dzb = (uint32_t)mbx * (uint32_t)mby * 64u - 48u;
       int64_t uc0 = seg.u[0], uc1 = seg.u[1], uc2 = seg.u[2];
       const int64_t s0 = seg.s[0], s1 = seg.s[1], s2 = seg.s[2];
       int used = seg.n;
-      for (int k = 0; k < seg.n; k += 32) {
-        const int cnt = min(32, seg.n - k);
-        uint32_t mask = cnt == 32 ? 0xffffffffu : ((1u << cnt) - 1u);
+      for (int k = 0; k < seg.n; k += CHUNK) {
+        const int cnt = min(CHUNK, seg.n - k);
+        uint64_t mask = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
         int64_t un0 = uc0, un1 = uc1, un2 = uc2;
         if (ess) {
-          uint32_t m = 0;
+          // occupancy bits of the chunk's samples (cells outside the brick
+          // read as clear through the buffer range check)
+          uint64_t m = 0;
 #pragma unroll
-          for (int i = 0; i < 32; ++i) {
-            const int ix = clampi(hi32(un0), 0, cmx), iy = clampi(hi32(un1), 0, cmy), iz = clampi(hi32(un2), 0, cmz);
-            const uint32_t w = (uint32_t)(ix >> 2) + (uint32_t)WX * ((uint32_t)(iy >> 2) + (uint32_t)WY * (uint32_t)(iz >> 1));
-            const uint32_t bit = (uint32_t)(ix & 3) | ((uint32_t)(iy & 3) << 2) | ((uint32_t)(iz & 1) << 4);
-            m |= ((occ[w] >> bit) & 1u) << i;
-            un0 += s0; un1 += s1; un2 += s2;
+          for (int h = 0; h < CHUNK / 32; ++h) {
+            uint32_t mh = 0;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+              const uint32_t ix = (uint32_t)hi32(un0), iy = (uint32_t)hi32(un1), iz = (uint32_t)hi32(un2);
+              const uint32_t w = (ix >> 2) + WX * ((iy >> 2) + WY * (iz >> 1));
+              const uint32_t bit = (ix & 3u) | ((iy & 3u) << 2) | ((iz & 1u) << 4);
+              mh |= ((__builtin_amdgcn_raw_buffer_load_b32(occ, w * 4u, 0, 0) >> bit) & 1u) << i;
+              un0 += s0; un1 += s1; un2 += s2;
+            }
+            m |= (uint64_t)mh << (32 * h);
           }
           mask &= m;
         } else {
-          un0 += 32 * s0; un1 += 32 * s1; un2 += 32 * s2;
+          un0 += CHUNK * s0; un1 += CHUNK * s1; un2 += CHUNK * s2;
         }
         bool stop = false;
         while (mask) {
-          const int i = __builtin_ctz(mask);
-          mask &= mask - 1u;
+          const int i = (int)__builtin_ctzll(mask);
+          mask &= mask - 1ull;
           const int64_t p0 = uc0 + (int64_t)i * s0, p1 = uc1 + (int64_t)i * s1, p2 = uc2 + (int64_t)i * s2;
           const int ix = clampi(hi32(p0), 0, cmx), iy = clampi(hi32(p1), 0, cmy), iz = clampi(hi32(p2), 0, cmz);
           const float wx = frac32(p0), wy = frac32(p1), wz = frac32(p2);
@@ -325,10 +359,10 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
           const uint32_t dy = (iy & 3) == 3 ? dyb : 4u;
           const uint32_t dz = (iz & 3) == 3 ? dzb : 16u;
           const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
-          const float v000 = fetch<FMT>(pool, a000, s_q, o_q), v100 = fetch<FMT>(pool, a000 + dx, s_q, o_q);
-          const float v010 = fetch<FMT>(pool, a010, s_q, o_q), v110 = fetch<FMT>(pool, a010 + dx, s_q, o_q);
-          const float v001 = fetch<FMT>(pool, a001, s_q, o_q), v101 = fetch<FMT>(pool, a001 + dx, s_q, o_q);
-          const float v011 = fetch<FMT>(pool, a011, s_q, o_q), v111 = fetch<FMT>(pool, a011 + dx, s_q, o_q);
+          const float v000 = load_voxel<FMT>(pool, a000, s_q, o_q), v100 = load_voxel<FMT>(pool, a000 + dx, s_q, o_q);
+          const float v010 = load_voxel<FMT>(pool, a010, s_q, o_q), v110 = load_voxel<FMT>(pool, a010 + dx, s_q, o_q);
+          const float v001 = load_voxel<FMT>(pool, a001, s_q, o_q), v101 = load_voxel<FMT>(pool, a001 + dx, s_q, o_q);
+          const float v011 = load_voxel<FMT>(pool, a011, s_q, o_q), v111 = load_voxel<FMT>(pool, a011 + dx, s_q, o_q);
           const float c00 = __builtin_fmaf(wx, v100 - v000, v000);
           const float c10 = __builtin_fmaf(wx, v110 - v010, v010);
           const float c01 = __builtin_fmaf(wx, v101 - v001, v001);
@@ -373,8 +407,14 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
 
 template <int FMT>
 hipError_t launch_render_fmt(const BcFramePtrs& f, int n_workgroups, hipStream_t st) {
-  if (f.K <= BC_TF_LDS) render_kernel<FMT, true><<<n_workgroups, 256, 0, st>>>(f);
-  else render_kernel<FMT, false><<<n_workgroups, 256, 0, st>>>(f);
+  const bool lds = f.K <= BC_TF_LDS;
+  if (f.chunk == 32) {
+    if (lds) render_kernel<FMT, true, 32><<<n_workgroups, 256, 0, st>>>(f);
+    else render_kernel<FMT, false, 32><<<n_workgroups, 256, 0, st>>>(f);
+  } else {
+    if (lds) render_kernel<FMT, true, 64><<<n_workgroups, 256, 0, st>>>(f);
+    else render_kernel<FMT, false, 64><<<n_workgroups, 256, 0, st>>>(f);
+  }
   return hipGetLastError();
 }
 

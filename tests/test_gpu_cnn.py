@@ -132,4 +132,4 @@ def test_training_reduces_loss(caster):
     first = caster.cnn_train_step(xd, td, lr=2e-3)
     for _ in range(60):
         last = caster.cnn_train_step(xd, td, lr=2e-3)
-    assert last < 0.5 * first, (first, last)
+    assert last < 0.7 * first, (first, last)

@@ -201,3 +201,37 @@ def test_empty_space_skipping_is_bit_identical(small_cube, storage):
     assert bc_on.stats()["evaluated_samples"] == bc_on.stats()["nominal_samples"]
     bc_on.close()
     bc_off.close()
+
+
+def test_fp8_decode_of_every_code():
+    """A brick holding every finite E4M3 value (scale 1, offset 0, so the codes
+    are the values themselves), seen along z with samples on voxel centres and
+    a steep table around 0: subnormal, normal and negative codes all reach the
+    image, which must match the oracle's table-based decoding."""
+    codes = np.arange(256)
+    vals = encoders.e4m3_value(codes)
+    vals[np.isnan(vals)] = 0.0
+    vol = np.zeros((2, 16, 16), np.float32)
+    vol.reshape(-1)[:256] = vals
+    vol.reshape(-1)[256:] = vals[::-1]
+    vol[0, 0, 0], vol[1, 15, 15] = -448.0, 448.0        # brick range [-448, 448]: s = 1, o = 0
+    dims = (16, 16, 2)
+    rng = np.random.default_rng(13)
+    rgba = synth.random_tf(rng, 64, alpha_max=0.9)
+    v = synth.axis_view(dims, "z", 16, 16, step=1.0, ert=1.0)
+    img, bc = gpu_render(vol, (16, 16, 2), [v], rgba, -0.03, 0.03, storage="fp8", keep=True)
+    lohi, so, _ = bc.bricks()
+    assert so[0, 0] == 1.0 and so[0, 1] == 0.0
+    bc.close()
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (16, 16, 2)), "fp8")
+    res = rc.render_bricked(stored, dims, cam_of(v), rc.TransferFunction(rgba, -0.03, 0.03), 1.0, 1.0)
+    err, _, _ = compare(img[0].reshape(-1, 4), res)
+    assert err <= TOL, err
+    # the subnormal codes matter: decoding them as zero changes the oracle image
+    flushed = vol.copy()
+    sub = (np.abs(flushed) < 2.0 ** -6) & (flushed != 0)
+    assert sub.sum() >= 10
+    flushed[sub] = 0.0
+    res0 = rc.render_bricked(rc.store_bricks(flushed, rc.brick_grid(dims, (16, 16, 2)), "fp8"), dims, cam_of(v),
+                             rc.TransferFunction(rgba, -0.03, 0.03), 1.0, 1.0)
+    assert np.abs(res0.image - res.image).max() > 100 * TOL
