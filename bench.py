@@ -48,9 +48,12 @@ HBM_PEAK_GBS = 8000.0
 ORBIT = 64
 
 WORKLOADS = {
-    # name: (recipe, brick edge, width, height)
-    "cube1024_persp1920x1080": (synth.RECIPE_1024, 256, 1920, 1080),
-    "cube128_ortho256": (synth.RECIPE_SMALL, 64, 256, 256),
+    # name: (recipe, brick edge, width, height, views per launch, source dtype)
+    "cube1024_persp1920x1080": (synth.RECIPE_1024, 256, 1920, 1080, 1, "f32"),
+    "cube128_ortho256": (synth.RECIPE_SMALL, 64, 256, 256, 1, "f32"),
+    # 3000 x 3000 x 1500 FP16 cube (27 GB), 12 x 12 x 6 bricks of 256^3 with
+    # uneven edge bricks, four orbit views 90 degrees apart per launch
+    "cube3000x3000x1500_f16_4views": (synth.RECIPE_BATCH, 256, 1920, 1080, 4, "f16"),
 }
 
 
@@ -72,6 +75,8 @@ def parse():
                    help="time learned frames: coarse render + trained upsampler, validated against plain tiles")
     p.add_argument("--weights", default=os.path.join(ROOT, "paper_1205_0282_amd", "weights", "upsampler.npy"))
     p.add_argument("--psnr-threshold", type=float, default=40.0)
+    p.add_argument("--graph", action="store_true", help="replay captured HIP graphs for the timed frames")
+    p.add_argument("--autotune", action="store_true", help="pick the launch shape by timing candidates first")
     p.add_argument("--frames", type=int, default=ORBIT,
                    help="distinct orbit frames cycled through (the first N of the 64-frame orbit)")
     p.add_argument("--check-pixels", type=int, default=1024,
@@ -83,6 +88,14 @@ def views_for(recipe, width, height):
     kind = "persp" if width != height else "ortho"
     return [synth.orbit_view(recipe.dims, k, ORBIT, kind=kind, width=width, height=height, step=0.5, ert=0.99)
             for k in range(ORBIT)]
+
+
+def view_sets(recipe, width, height, per_launch, n):
+    """Launch i renders orbit frames i, i + 64/v, ... (v views per launch)."""
+    orbit = views_for(recipe, width, height)
+    stride = ORBIT // per_launch
+    n_sets = max(1, min(stride, n))
+    return [[orbit[i + j * stride] for j in range(per_launch)] for i in range(n_sets)]
 
 
 # ------------------------------------------------------------------ CPU oracle
@@ -218,14 +231,21 @@ def main():
         print("bench.py: this build measures one GPU only; --gpus must be 1 (no multi-GPU path is built)",
               file=sys.stderr)
         sys.exit(2)
-    recipe, brick, W, H = WORKLOADS[args.workload]
+    recipe, brick, W, H, per_launch, src_dtype = WORKLOADS[args.workload]
+    if per_launch > 1 and (args.learned or args.check_pixels or args.cpu_seconds):
+        log("batched workload: learned mode, oracle check and CPU baseline are not run")
+        args.learned, args.check_pixels, args.cpu_seconds = False, 0, 0
+    if src_dtype == "f16" and args.storage == "f32":
+        args.storage = "f16"
     t = time.perf_counter()
-    vol = synth.make_cube(recipe, workers=min(16, os.cpu_count() or 1))
+    vol = synth.make_cube(recipe, workers=min(16, os.cpu_count() or 1),
+                          out_dtype=np.float16 if src_dtype == "f16" else np.float32)
     vmin, vmax = float(vol.min()), float(vol.max())
     log(f"cube {recipe.dims} generated in {time.perf_counter() - t:.1f} s; range [{vmin:.3f}, {vmax:.3f}]")
     rgba = synth.ramp_tf(vmin, vmax)
-    views = views_for(recipe, W, H)[:max(1, min(ORBIT, args.frames))]
-    nf = len(views)
+    sets = view_sets(recipe, W, H, per_launch, args.frames)
+    views = [vs[0] for vs in sets]
+    nf = len(sets)
 
     workers = args.cpu_workers or min(16, os.cpu_count() or 1)
     ref = None
@@ -243,7 +263,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     bc = binding.BrickCaster(0)
-    bc.plan(recipe.dims, (brick,) * 3, storage=args.storage, src_dtype="f32", max_views=1, max_w=W, max_h=H)
+    bc.plan(recipe.dims, (brick,) * 3, storage=args.storage, src_dtype=src_dtype, max_views=per_launch,
+            max_w=W, max_h=H)
     bc.bind()
     t = time.perf_counter()
     src = torch.from_numpy(vol).to(dev)
@@ -254,22 +275,25 @@ def main():
     torch.cuda.empty_cache()
     log(f"bricks loaded in {time.perf_counter() - t:.1f} s")
     bc.set_transfer_function(rgba, vmin, vmax)
-    out = torch.empty((1, H, W, 4), dtype=torch.float32, device=dev)
+    out = torch.empty((per_launch, H, W, 4), dtype=torch.float32, device=dev)
 
     # per orbit frame: samples and algorithmic bytes of the ray-casting launch (untimed)
     lohi, _, _ = bc.bricks()
     ebytes = {"f32": 4, "f16": 2, "fp8": 1}[args.storage]
     core_bytes = np.prod((lohi[:, 3:] - lohi[:, :3]).astype(np.int64), axis=1) * ebytes
     samples, evaluated, algo_bytes, tiles = [], [], [], []
-    for v in views:
-        bc.set_views([v])
+    for vs in sets:
+        bc.set_views(vs)
         bc.render(out)
         st = bc.stats()
-        r = bc.rects(0)
-        live = (r[:, 2] > r[:, 0]) & (r[:, 3] > r[:, 1])
+        live = np.zeros(len(core_bytes), bool)
+        for j in range(len(vs)):
+            r = bc.rects(j)
+            live |= (r[:, 2] > r[:, 0]) & (r[:, 3] > r[:, 1])
         samples.append(st["nominal_samples"])
         evaluated.append(st["evaluated_samples"])
         tiles.append(st["n_tiles"])
+        # each voxel of a brick any view needs is read once per launch
         algo_bytes.append(int(core_bytes[live].sum()) + st["n_tiles"] * 64 * 16)
     log(f"orbit: mean {np.mean(samples) / 1e6:.1f} M samples/frame, {np.mean(tiles):.0f} tiles/frame")
 
@@ -285,15 +309,32 @@ def main():
     if args.learned:
         learned = setup_learned(bc, args, views, out, W, H)
 
+    tuned = None
+    if args.autotune:
+        bc.set_views(sets[0])
+        tuned = bc.autotune(out, frames=3)
+        log(f"autotune: chunk {tuned[0]}, workgroups {tuned[1]}")
+    stage_ms_eager = None
+    if args.graph:
+        # stage split from eager frames first (a graph is timed as a whole)
+        bc.enable_timing(True)
+        for i in range(min(args.steps, nf)):
+            bc.set_views(sets[i % nf])
+            bc.render(out)
+        ms, k = bc.timing()
+        stage_ms_eager = [m / k for m in ms]
+        bc.enable_timing(False)
+        bc.set_option(binding.BC_OPT_GRAPH, 1)
+
     for i in range(args.warmup):
-        bc.set_views([views[i % nf]])
+        bc.set_views(sets[i % nf])
         bc.render(out)
     torch.cuda.synchronize()
     bc.enable_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        bc.set_views([views[i % nf]])
+        bc.set_views(sets[i % nf])
         bc.render(out)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -304,11 +345,14 @@ def main():
     idx = [i % nf for i in range(args.steps)]
     tot_samples = float(sum(samples[i] for i in idx))
     tot_bytes = float(sum(algo_bytes[i] for i in idx))
+    if stage_ms_eager is not None:
+        stage_ms = [m * n_timed for m in stage_ms_eager]
     render_s = stage_ms[1] / 1e3
     achieved = tot_bytes / render_s / 1e9
     ms_step = elapsed / args.steps * 1e3
     result = {
-        "metric": "Gsamples/s + fps @1920x1080 on 1024^3 cube",
+        "metric": "Gsamples/s + fps @1920x1080 on 1024^3 cube" if per_launch == 1 else
+                  "Gsamples/s + launches/s @1920x1080, 4 views per launch, 3000x3000x1500 FP16 cube",
         "value": tot_samples / elapsed / 1e9,   # learned frames: nominal samples of the plain frame (equivalent)
         "unit": "Gsamples/s",
         "n_gpus": 1,
@@ -324,7 +368,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cube": list(recipe.dims), "brick": brick,
                    "image": [W, H], "step_vox": 0.5, "ert": 0.99, "storage": args.storage,
-                   "orbit_frames": nf, "views_per_launch": 1},
+                   "orbit_frames": nf * per_launch, "views_per_launch": per_launch,
+                   "graph": bool(args.graph), "autotuned": tuned},
         "stage_ms_per_frame": {"setup": stage_ms[0] / n_timed, "render": stage_ms[1] / n_timed,
                                "composite": stage_ms[2] / n_timed},
         "samples_per_frame": tot_samples / args.steps,

@@ -186,9 +186,25 @@ int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);
  *  BC_OPT_SAMPLE_CHUNK (32 or 64, default 64): samples per ray whose
  *    occupancy is gathered before the occupied ones are evaluated.  Images do
  *    not depend on it.
+ *  BC_OPT_GRAPH (default 0): 1 captures each frame's uploads and kernels once
+ *    into a HIP graph (one per per-frame input buffer; captured again when the
+ *    view count, frame size, table size, launch options, mode or `out` change)
+ *    and replays it; images are identical.  With a graph, timing reports the
+ *    whole frame in stage 1 (ray casting) and zero for the other stages.
  * Errors: BC_E_ARG for an unknown option or a value out of range. */
-enum bc_option { BC_OPT_EMPTY_SKIP = 0, BC_OPT_RENDER_WORKGROUPS = 1, BC_OPT_SAMPLE_CHUNK = 2 };
+enum bc_option { BC_OPT_EMPTY_SKIP = 0, BC_OPT_RENDER_WORKGROUPS = 1, BC_OPT_SAMPLE_CHUNK = 2, BC_OPT_GRAPH = 3 };
 int bc_set_option(bc_ctx* ctx, int option, int64_t value);
+
+/* Autotuner: renders the current views (plain frames) with every candidate
+ * launch shape -- samples per occupancy chunk in {32, 64} times persistent
+ * workgroups in {2, 4, 6, 8} per compute unit -- for `frames` timed frames each
+ * (after one warm-up frame per candidate), measures the ray-casting kernel with
+ * HIP events and keeps the fastest; chosen[0] = chunk, chosen[1] = workgroups
+ * (chosen may be NULL).  Writes frames into `out` (same contract as
+ * bc_render_frame) and waits for them.  The result applies to later frames
+ * (also settable with bc_set_option).  Errors: as bc_render_frame; BC_E_ARG
+ * for frames outside [1, 64]; BC_E_STATE with learned frames on. */
+int bc_autotune(bc_ctx* ctx, float* out, void* stream, int frames, int64_t chosen[2]);
 
 /* Per-stage GPU time, measured with HIP events recorded on the frame's own
  * stream.  bc_enable_timing(ctx, 1) waits for the last frame and opens a new

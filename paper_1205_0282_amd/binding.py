@@ -25,10 +25,10 @@ EXPORTS = [
     "bc_get_bricks", "bc_get_visibility_order", "bc_get_rects", "bc_read_brick",
     "bc_enable_timing", "bc_get_timing", "bc_set_option",
     "bc_cnn_plan", "bc_cnn_bind", "bc_cnn_set_weights", "bc_cnn_get_weights", "bc_cnn_forward",
-    "bc_cnn_gradients", "bc_cnn_train_step", "bc_set_learned",
+    "bc_cnn_gradients", "bc_cnn_train_step", "bc_set_learned", "bc_autotune",
 ]
 CNN_N_PARAMS = 15056
-BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS, BC_OPT_SAMPLE_CHUNK = 0, 1, 2
+BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS, BC_OPT_SAMPLE_CHUNK, BC_OPT_GRAPH = 0, 1, 2, 3
 
 
 class LibraryMissing(RuntimeError):
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
         "bc_set_option": (I, [P, I, I64]),
         "bc_cnn_plan": (I, [P, I, I, I, C.POINTER(C.c_size_t)]),
         "bc_set_learned": (I, [P, I, D, D, I]),
+        "bc_autotune": (I, [P, P, P, I, C.POINTER(C.c_int64)]),
         "bc_cnn_bind": (I, [P, P, C.c_size_t]),
         "bc_cnn_set_weights": (I, [P, C.POINTER(F), C.POINTER(F), C.POINTER(F), C.c_size_t, I64]),
         "bc_cnn_get_weights": (I, [P, C.POINTER(F), C.POINTER(F), C.POINTER(F), C.c_size_t, C.POINTER(I64)]),
@@ -235,6 +236,18 @@ class BrickCaster:
         n = C.c_int()
         self._check(self.lib.bc_get_timing(self.h, ms, C.byref(n)))
         return [float(x) for x in ms], int(n.value)
+
+    def autotune(self, out=None, frames=3, stream=None):
+        """Times every candidate launch shape on the current views and keeps
+        the fastest; returns (chunk, workgroups)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_views, self.height, self.width, 4), dtype=torch.float32,
+                              device=torch.device("cuda", self.device))
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        ch = (C.c_int64 * 2)()
+        self._check(self.lib.bc_autotune(self.h, C.c_void_p(out.data_ptr()), C.c_void_p(st), int(frames), ch))
+        return int(ch[0]), int(ch[1])
 
     def set_learned(self, enable=True, coarse_step=2.0, psnr_threshold_db=40.0, validate_stride=8):
         self._check(self.lib.bc_set_learned(self.h, 1 if enable else 0, float(coarse_step),

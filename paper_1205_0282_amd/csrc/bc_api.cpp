@@ -21,6 +21,20 @@ namespace {
 
 thread_local std::string g_create_error;
 
+struct GraphKey {
+  bool learned = false, ess = false;
+  int n_views = 0, W = 0, H = 0, K = 0, chunk = 0, wgs = 0;
+  const void* out = nullptr;
+  bool operator==(const GraphKey& o) const {
+    return learned == o.learned && ess == o.ess && n_views == o.n_views && W == o.W && H == o.H && K == o.K &&
+           chunk == o.chunk && wgs == o.wgs && out == o.out;
+  }
+};
+struct GraphSlot {
+  hipGraphExec_t exec = nullptr;
+  GraphKey key;
+};
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kMaxTimedFrames = 4096;
@@ -66,6 +80,10 @@ struct bc_ctx {
   int render_workgroups = 0;
   bool ess = true;
   int chunk = 64;
+  // captured frames (one per input slot)
+  bool use_graph = false;
+  hipStream_t capture_stream = nullptr;
+  GraphSlot graphs[2];
   // cell-occupancy bits are valid for this table (opacity-corrected entries)
   bool occ_valid = false;
   std::vector<float> occ_table;
@@ -360,6 +378,7 @@ int bc_create(int hip_device, bc_ctx** out) {
       ok = ok && hipEventCreateWithFlags(&c->copy_done[i], hipEventDisableTiming) == hipSuccess;
     }
     ok = ok && hipEventCreateWithFlags(&c->frame_done, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
       g_create_error = "bc_create: cannot allocate pinned frame buffers / events";
       bc_destroy(c);
@@ -381,6 +400,9 @@ void bc_destroy(bc_ctx* c) {
     }
     if (c->frame_done) (void)hipEventDestroy(c->frame_done);
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    for (GraphSlot& g : c->graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->load_staging) (void)hipHostFree(c->load_staging);
   }
   delete c;
@@ -688,12 +710,8 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     spec.reset = ps == 0;
     spec.conditional = c->learned && ps == 2;
     fill_pass(c, pins + ps, spec);
-    const size_t bytes = offsetof(BcFrameIn, table) + sizeof(float) * 4 * c->K;
-    HIPCHECK(c, hipMemcpyAsync(meta + c->off_fin + sizeof(BcFrameIn) * ps, pins + ps, bytes, hipMemcpyHostToDevice,
-                               st));
   }
-  HIPCHECK(c, hipEventRecord(c->copy_done[slot], st));
-  c->copy_pending[slot] = true;
+  const size_t fin_bytes = offsetof(BcFrameIn, table) + sizeof(float) * 4 * c->K;
   c->frame_views = n;
   // empty-space classification depends only on which table entries are zero
   // (and on the value-to-table mapping): redo it when that pattern changes
@@ -722,37 +740,97 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     ++c->timed_frames;
   }
   BcFramePtrs f = frame_ptrs(c);
-  if (classify) HIPCHECK(c, bc_launch_classify(f, c->max_occ_words, st));
-  if (ev) HIPCHECK(c, hipEventRecord(ev[0], st));
-  if (!c->learned) {
-    HIPCHECK(c, bc_launch_setup(f, st));
-    if (ev) HIPCHECK(c, hipEventRecord(ev[1], st));
-    HIPCHECK(c, bc_launch_render(f, c->render_workgroups, st));
-    if (ev) HIPCHECK(c, hipEventRecord(ev[2], st));
-    HIPCHECK(c, bc_launch_composite(f, reinterpret_cast<float4*>(out), st));
-  } else {
-    const CnnLayout L = cnn_layout(c->cnn_max_n, c->cnn_max_h, c->cnn_max_w);
-    float* coarse_img = reinterpret_cast<float*>(c->cnn_ws + L.coarse);
-    float* val_img = reinterpret_cast<float*>(c->cnn_ws + L.val);
-    BcFramePtrs fc = pass_ptrs(c, f, 0, W / 2, H / 2);
-    HIPCHECK(c, bc_launch_setup(fc, st));
-    HIPCHECK(c, bc_launch_render(fc, c->render_workgroups, st));
-    HIPCHECK(c, bc_launch_composite(fc, reinterpret_cast<float4*>(coarse_img), st));
-    if (ev) HIPCHECK(c, hipEventRecord(ev[1], st));
-    int r = cnn_infer(c, L, coarse_img, out, n, H / 2, W / 2, st);
-    if (r) return r;
-    if (ev) HIPCHECK(c, hipEventRecord(ev[2], st));
-    BcFramePtrs fv = pass_ptrs(c, f, 1, W, H);
-    HIPCHECK(c, bc_launch_setup(fv, st));
-    HIPCHECK(c, bc_launch_render(fv, c->render_workgroups, st));
-    HIPCHECK(c, bc_launch_composite(fv, reinterpret_cast<float4*>(val_img), st));
-    HIPCHECK(c, bc_launch_psnr(fv, reinterpret_cast<const float4*>(val_img), reinterpret_cast<const float4*>(out), st));
-    BcFramePtrs fp = pass_ptrs(c, f, 2, W, H);
-    HIPCHECK(c, bc_launch_setup(fp, st));
-    HIPCHECK(c, bc_launch_render(fp, c->render_workgroups, st));
-    HIPCHECK(c, bc_launch_composite(fp, reinterpret_cast<float4*>(out), st));
+  if (classify) {
+    HIPCHECK(c, hipMemcpyAsync(meta + c->off_fin, pins, fin_bytes, hipMemcpyHostToDevice, st));
+    HIPCHECK(c, bc_launch_classify(f, c->max_occ_words, st));
   }
-  if (ev) HIPCHECK(c, hipEventRecord(ev[3], st));
+  // the frame: upload of the pass inputs, then the kernels of every pass
+  auto enqueue = [&](hipStream_t s, hipEvent_t* e) -> int {
+    for (int ps = 0; ps < passes; ++ps)
+      HIPCHECK(c, hipMemcpyAsync(meta + c->off_fin + sizeof(BcFrameIn) * ps, pins + ps, fin_bytes,
+                                 hipMemcpyHostToDevice, s));
+    if (e) HIPCHECK(c, hipEventRecord(e[0], s));
+    if (!c->learned) {
+      HIPCHECK(c, bc_launch_setup(f, s));
+      if (e) HIPCHECK(c, hipEventRecord(e[1], s));
+      HIPCHECK(c, bc_launch_render(f, c->render_workgroups, s));
+      if (e) HIPCHECK(c, hipEventRecord(e[2], s));
+      HIPCHECK(c, bc_launch_composite(f, reinterpret_cast<float4*>(out), s));
+    } else {
+      const CnnLayout L = cnn_layout(c->cnn_max_n, c->cnn_max_h, c->cnn_max_w);
+      float* coarse_img = reinterpret_cast<float*>(c->cnn_ws + L.coarse);
+      float* val_img = reinterpret_cast<float*>(c->cnn_ws + L.val);
+      BcFramePtrs fc = pass_ptrs(c, f, 0, W / 2, H / 2);
+      HIPCHECK(c, bc_launch_setup(fc, s));
+      HIPCHECK(c, bc_launch_render(fc, c->render_workgroups, s));
+      HIPCHECK(c, bc_launch_composite(fc, reinterpret_cast<float4*>(coarse_img), s));
+      if (e) HIPCHECK(c, hipEventRecord(e[1], s));
+      int r = cnn_infer(c, L, coarse_img, out, n, H / 2, W / 2, s);
+      if (r) return r;
+      if (e) HIPCHECK(c, hipEventRecord(e[2], s));
+      BcFramePtrs fv = pass_ptrs(c, f, 1, W, H);
+      HIPCHECK(c, bc_launch_setup(fv, s));
+      HIPCHECK(c, bc_launch_render(fv, c->render_workgroups, s));
+      HIPCHECK(c, bc_launch_composite(fv, reinterpret_cast<float4*>(val_img), s));
+      HIPCHECK(c, bc_launch_psnr(fv, reinterpret_cast<const float4*>(val_img), reinterpret_cast<const float4*>(out), s));
+      BcFramePtrs fp = pass_ptrs(c, f, 2, W, H);
+      HIPCHECK(c, bc_launch_setup(fp, s));
+      HIPCHECK(c, bc_launch_render(fp, c->render_workgroups, s));
+      HIPCHECK(c, bc_launch_composite(fp, reinterpret_cast<float4*>(out), s));
+    }
+    if (e) HIPCHECK(c, hipEventRecord(e[3], s));
+    return BC_OK;
+  };
+  if (!c->use_graph) {
+    int r = enqueue(st, ev);
+    if (r) return r;
+  } else {
+    // one captured graph per input slot (its copies read that slot's pinned
+    // buffer); re-captured when anything baked into the launches changes
+    GraphKey key;
+    key.learned = c->learned;
+    key.n_views = n;
+    key.W = W;
+    key.H = H;
+    key.K = c->K;
+    key.chunk = c->chunk;
+    key.ess = c->ess;
+    key.wgs = c->render_workgroups;
+    key.out = out;
+    GraphSlot& g = c->graphs[slot];
+    if (!g.exec || !(g.key == key)) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
+      hipGraph_t graph = nullptr;
+      HIPCHECK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+      int r = enqueue(c->capture_stream, nullptr);
+      hipError_t ec = hipStreamEndCapture(c->capture_stream, &graph);
+      if (r) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+      }
+      if (ec != hipSuccess) return fail(c, BC_E_HIP, "bc_render_frame: graph capture: %s", hipGetErrorString(ec));
+      ec = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ec != hipSuccess) {
+        g.exec = nullptr;
+        return fail(c, BC_E_HIP, "bc_render_frame: graph instantiation: %s", hipGetErrorString(ec));
+      }
+      g.key = key;
+    }
+    // with a graph only the whole frame is timed (stage slot 1)
+    if (ev) {
+      HIPCHECK(c, hipEventRecord(ev[0], st));
+      HIPCHECK(c, hipEventRecord(ev[1], st));
+    }
+    HIPCHECK(c, hipGraphLaunch(g.exec, st));
+    if (ev) {
+      HIPCHECK(c, hipEventRecord(ev[2], st));
+      HIPCHECK(c, hipEventRecord(ev[3], st));
+    }
+  }
+  HIPCHECK(c, hipEventRecord(c->copy_done[slot], st));
+  c->copy_pending[slot] = true;
   HIPCHECK(c, hipEventRecord(c->frame_done, st));
   c->frame_pending = true;
   c->last_learned = c->learned;
@@ -805,6 +883,15 @@ int bc_set_option(bc_ctx* c, int option, int64_t value) {
       if (value != 32 && value != 64) return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_SAMPLE_CHUNK takes 32 or 64");
       c->chunk = (int)value;
       return BC_OK;
+    case BC_OPT_GRAPH:
+      if (value != 0 && value != 1) return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_GRAPH takes 0 or 1");
+      if (c->device >= 0) {
+        HIPCHECK(c, hipSetDevice(c->device));
+        int r = wait_frame(c);
+        if (r) return r;
+      }
+      c->use_graph = value != 0;
+      return BC_OK;
     case BC_OPT_RENDER_WORKGROUPS:
       if (value < 1 || value > (1 << 20))
         return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_RENDER_WORKGROUPS outside [1, 2^20]");
@@ -813,6 +900,57 @@ int bc_set_option(bc_ctx* c, int option, int64_t value) {
     default:
       return fail(c, BC_E_ARG, "bc_set_option: unknown option %d", option);
   }
+}
+
+int bc_autotune(bc_ctx* c, float* out, void* stream, int frames, int64_t chosen[2]) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (frames < 1 || frames > 64) return fail(c, BC_E_ARG, "bc_autotune: frames outside [1, 64]");
+  if (c->device < 0) return fail(c, BC_E_STATE, "bc_autotune: host-only context");
+  if (c->learned) return fail(c, BC_E_STATE, "bc_autotune: tune with learned frames off");
+  HIPCHECK(c, hipSetDevice(c->device));
+  int r = wait_frame(c);
+  if (r) return r;
+  const bool timing = c->timing, graph = c->use_graph;
+  const int chunk0 = c->chunk, wgs0 = c->render_workgroups;
+  c->use_graph = false;
+  const int chunks[2] = {32, 64};
+  const int per_cu[4] = {2, 4, 6, 8};
+  double best = 1e300;
+  int best_chunk = chunk0, best_wgs = wgs0;
+  // one untimed frame first: classification and caches
+  r = bc_render_frame(c, out, stream);
+  for (int ci = 0; ci < 2 && !r; ++ci)
+    for (int wi = 0; wi < 4 && !r; ++wi) {
+      c->chunk = chunks[ci];
+      c->render_workgroups = c->n_cu * per_cu[wi];
+      c->timing = true;
+      c->timed_frames = 0;
+      for (int k = 0; k < frames + 1 && !r; ++k) {
+        if (k == 1) c->timed_frames = 0;   // the first frame of a candidate warms it up
+        r = bc_render_frame(c, out, stream);
+      }
+      if (r) break;
+      double ms[3];
+      int nf = 0;
+      r = bc_get_timing(c, ms, &nf);
+      if (!r && nf > 0 && ms[1] / nf < best) {
+        best = ms[1] / nf;
+        best_chunk = c->chunk;
+        best_wgs = c->render_workgroups;
+      }
+    }
+  c->timing = timing;
+  c->timed_frames = 0;
+  c->use_graph = graph;
+  c->chunk = r ? chunk0 : best_chunk;
+  c->render_workgroups = r ? wgs0 : best_wgs;
+  if (r) return r;
+  if (chosen) {
+    chosen[0] = best_chunk;
+    chosen[1] = best_wgs;
+  }
+  return BC_OK;
 }
 
 int bc_enable_timing(bc_ctx* c, int enable) {

@@ -235,3 +235,43 @@ def test_fp8_decode_of_every_code():
     res0 = rc.render_bricked(rc.store_bricks(flushed, rc.brick_grid(dims, (16, 16, 2)), "fp8"), dims, cam_of(v),
                              rc.TransferFunction(rgba, -0.03, 0.03), 1.0, 1.0)
     assert np.abs(res0.image - res.image).max() > 100 * TOL
+
+
+def test_graph_frames_match_eager_frames(small_cube):
+    """Captured frames replayed many times, with eager frames and host syncs in
+    between, give the eager frames bit for bit (one graph per input slot)."""
+    import torch
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    views = [synth.orbit_view(vol.shape[::-1], f, kind="persp", width=96, height=72) for f in range(0, 64, 9)]
+    _, eager = gpu_render(vol, (64, 64, 64), views[:1], rgba, vmin, vmax, keep=True)
+    refs = []
+    for v in views:
+        eager.set_views([v])
+        refs.append(eager.render().clone())
+    _, g = gpu_render(vol, (64, 64, 64), views[:1], rgba, vmin, vmax, keep=True,
+                      options={binding.BC_OPT_GRAPH: 1})
+    out = torch.empty_like(refs[0])
+    for rep in range(3):
+        for i, v in enumerate(views):
+            g.set_views([v])
+            g.render(out)
+            torch.cuda.synchronize()
+            assert torch.equal(out, refs[i]), (rep, i)
+            eager.set_views([views[-1 - i]])
+            eager.render()
+    g.close()
+    eager.close()
+
+
+def test_autotune_keeps_the_image(small_cube):
+    import torch
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    v = synth.orbit_view(vol.shape[::-1], 11, kind="persp", width=128, height=96)
+    img, bc = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax, keep=True)
+    chunk, wgs = bc.autotune(frames=2)
+    assert chunk in (32, 64) and wgs > 0
+    again = bc.render().cpu().numpy()
+    assert np.array_equal(again, img.astype(np.float32))
+    bc.close()
