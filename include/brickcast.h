@@ -183,7 +183,7 @@ int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);
  *    the opacity-corrected table changes.
  *  BC_OPT_RENDER_WORKGROUPS: workgroups (256 threads) of the persistent
  *    ray-casting launch; default 8 per compute unit.
- *  BC_OPT_SAMPLE_CHUNK (32 or 64, default 64): samples per ray whose
+ *  BC_OPT_SAMPLE_CHUNK (32 or 64, default 32): samples per ray whose
  *    occupancy is gathered before the occupied ones are evaluated.  Images do
  *    not depend on it.
  *  BC_OPT_GRAPH (default 0): 1 captures each frame's uploads and kernels once

@@ -79,7 +79,7 @@ struct bc_ctx {
   // kernel launch shape and options
   int render_workgroups = 0;
   bool ess = true;
-  int chunk = 64;
+  int chunk = 32;
   // captured frames (one per input slot)
   bool use_graph = false;
   hipStream_t capture_stream = nullptr;

@@ -57,9 +57,16 @@ __device__ __forceinline__ float fetch(const void* __restrict__ pool, uint32_t i
 }
 
 // Buffer resources: the hardware range check turns an offset outside the
-// brick (or its occupancy bits) into a zero instead of a fault.
+// brick (or its occupancy bits) into a zero instead of a fault.  Base and size
+// are made wave-uniform explicitly so that the resource lives in scalar
+// registers (a resource the compiler cannot prove uniform is rebuilt lane by
+// lane around every load).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  void* ub = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
 template <int FMT>
@@ -72,7 +79,7 @@ __device__ __forceinline__ float load_voxel(__amdgpu_buffer_rsrc_t r, uint32_t i
 // element index, inside the brick, of ghosted local voxel (x, y, z): 4x4x4
 // micro-blocks stored row-major, voxels of a micro-block x fastest
 __device__ __forceinline__ uint32_t vox_index(int x, int y, int z, int mbx, int mby) {
-  const uint32_t blk = (uint32_t)(x >> 2) + (uint32_t)mbx * ((uint32_t)(y >> 2) + (uint32_t)mby * (uint32_t)(z >> 2));
+  const uint32_t blk = (uint32_t)(x >> 2) + __umul24((uint32_t)mbx, (uint32_t)(y >> 2) + __umul24((uint32_t)mby, (uint32_t)(z >> 2)));
   return (blk << 6) | ((uint32_t)(z & 3) << 4) | ((uint32_t)(y & 3) << 2) | (uint32_t)(x & 3);
 }
 
@@ -268,7 +275,8 @@ __device__ __forceinline__ float frac32(int64_t v) { return (float)(uint32_t)v *
 // ------------------------------------------------------------------ render
 template <int FMT, bool TF_LDS, int CHUNK>
 __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
-  __shared__ float4 s_tab[TF_LDS ? BC_TF_LDS : 1];
+  // table entry k at 2k, its difference to entry k+1 at 2k+1
+  __shared__ float4 s_tab[TF_LDS ? 2 * BC_TF_LDS : 2];
   const int lane = threadIdx.x & 63;
   const BcFrameIn* fin = f.fin;
   const int K = fin->K;
@@ -276,10 +284,14 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
   const float kmax_f = (float)(K - 1);
   const float4* gtab = reinterpret_cast<const float4*>(fin->table);
   if (TF_LDS) {
-    for (int k = threadIdx.x; k < K; k += blockDim.x) s_tab[k] = gtab[k];
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      const float4 a = gtab[k], b = gtab[min(k + 1, K - 1)];
+      s_tab[2 * k] = a;
+      s_tab[2 * k + 1] = make_float4(b.x - a.x, b.y - a.y, b.z - a.z, b.w - a.w);
+    }
     __syncthreads();
   }
-  const float4* tab = TF_LDS ? s_tab : gtab;
+
   const int nv = f.n_views, nb = f.n_bricks;
   const int KB = nb * nv;
   const uint32_t n_items = f.ctr->n_items;
@@ -321,6 +333,8 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
       const uint32_t dxb = 61u, dyb = (uint32_t)mbx * 64u - 12u, dzb = (uint32_t)mbx * (uint32_t)mby * 64u - 48u;
       int64_t uc0 = seg.u[0], uc1 = seg.u[1], uc2 = seg.u[2];
       const int64_t s0 = seg.s[0], s1 = seg.s[1], s2 = seg.s[2];
+      const float sfx = (float)s0 * 2.3283064365386963e-10f, sfy = (float)s1 * 2.3283064365386963e-10f,
+                  sfz = (float)s2 * 2.3283064365386963e-10f;
       int used = seg.n;
       for (int k = 0; k < seg.n; k += CHUNK) {
         const int cnt = min(CHUNK, seg.n - k);
@@ -329,63 +343,89 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
         if (ess) {
           // occupancy bits of the chunk's samples (cells outside the brick
           // read as clear through the buffer range check)
+          // all addresses first, then all loads in flight together
           uint64_t m = 0;
 #pragma unroll
-          for (int h = 0; h < CHUNK / 32; ++h) {
-            uint32_t mh = 0;
+          for (int h = 0; h < CHUNK / 16; ++h) {
+            uint32_t wofs[16], bit[16], word[16];
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
+            for (int i = 0; i < 16; ++i) {
               const uint32_t ix = (uint32_t)hi32(un0), iy = (uint32_t)hi32(un1), iz = (uint32_t)hi32(un2);
-              const uint32_t w = (ix >> 2) + WX * ((iy >> 2) + WY * (iz >> 1));
-              const uint32_t bit = (ix & 3u) | ((iy & 3u) << 2) | ((iz & 1u) << 4);
-              mh |= ((__builtin_amdgcn_raw_buffer_load_b32(occ, w * 4u, 0, 0) >> bit) & 1u) << i;
+              wofs[i] = ((ix >> 2) + __umul24(WX, (iy >> 2) + __umul24(WY, iz >> 1))) * 4u;
+              bit[i] = (ix & 3u) | ((iy & 3u) << 2) | ((iz & 1u) << 4);
               un0 += s0; un1 += s1; un2 += s2;
             }
-            m |= (uint64_t)mh << (32 * h);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) word[i] = __builtin_amdgcn_raw_buffer_load_b32(occ, wofs[i], 0, 0);
+            uint32_t mh = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) mh |= ((word[i] >> bit[i]) & 1u) << i;
+            m |= (uint64_t)mh << (16 * h);
           }
           mask &= m;
         } else {
           un0 += CHUNK * s0; un1 += CHUNK * s1; un2 += CHUNK * s2;
         }
         bool stop = false;
-        while (mask) {
-          const int i = (int)__builtin_ctzll(mask);
-          mask &= mask - 1ull;
-          const int64_t p0 = uc0 + (int64_t)i * s0, p1 = uc1 + (int64_t)i * s1, p2 = uc2 + (int64_t)i * s2;
-          const int ix = clampi(hi32(p0), 0, cmx), iy = clampi(hi32(p1), 0, cmy), iz = clampi(hi32(p2), 0, cmz);
-          const float wx = frac32(p0), wy = frac32(p1), wz = frac32(p2);
-          const uint32_t a000 = vox_index(ix, iy, iz, mbx, mby);
-          const uint32_t dx = (ix & 3) == 3 ? dxb : 1u;
-          const uint32_t dy = (iy & 3) == 3 ? dyb : 4u;
-          const uint32_t dz = (iz & 3) == 3 ? dzb : 16u;
-          const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
-          const float v000 = load_voxel<FMT>(pool, a000, s_q, o_q), v100 = load_voxel<FMT>(pool, a000 + dx, s_q, o_q);
-          const float v010 = load_voxel<FMT>(pool, a010, s_q, o_q), v110 = load_voxel<FMT>(pool, a010 + dx, s_q, o_q);
-          const float v001 = load_voxel<FMT>(pool, a001, s_q, o_q), v101 = load_voxel<FMT>(pool, a001 + dx, s_q, o_q);
-          const float v011 = load_voxel<FMT>(pool, a011, s_q, o_q), v111 = load_voxel<FMT>(pool, a011 + dx, s_q, o_q);
-          const float c00 = __builtin_fmaf(wx, v100 - v000, v000);
-          const float c10 = __builtin_fmaf(wx, v110 - v010, v010);
-          const float c01 = __builtin_fmaf(wx, v101 - v001, v001);
-          const float c11 = __builtin_fmaf(wx, v111 - v011, v011);
-          const float c0 = __builtin_fmaf(wy, c10 - c00, c00);
-          const float c1 = __builtin_fmaf(wy, c11 - c01, c01);
-          const float val = __builtin_fmaf(wz, c1 - c0, c0);
-          float xt = __builtin_fmaf(val, tf_scale, tf_bias);
-          xt = fminf(fmaxf(xt, 0.0f), kmax_f);
-          const int it = min((int)xt, K - 2);
-          const float ft = xt - (float)it;
-          const float4 q0 = tab[it];
-          const float4 q1 = tab[it + 1];
-          const float om = 1.0f - acc.w;
-          acc.x = __builtin_fmaf(om, __builtin_fmaf(ft, q1.x - q0.x, q0.x), acc.x);
-          acc.y = __builtin_fmaf(om, __builtin_fmaf(ft, q1.y - q0.y, q0.y), acc.y);
-          acc.z = __builtin_fmaf(om, __builtin_fmaf(ft, q1.z - q0.z, q0.z), acc.z);
-          acc.w = __builtin_fmaf(om, __builtin_fmaf(ft, q1.w - q0.w, q0.w), acc.w);
-          ++evaluated;
-          if (acc.w >= tau) {
-            used = k + i + 1;
-            stop = true;
-            break;
+        if (mask) {
+          // sample positions inside the chunk in FP32, relative to the
+          // chunk's first sample: integer cell of that sample plus a
+          // fraction that stays below 1 + CHUNK/2 voxels
+          const int bx = hi32(uc0), by = hi32(uc1), bz = hi32(uc2);
+          const float fx0 = frac32(uc0), fy0 = frac32(uc1), fz0 = frac32(uc2);
+          for (int half = 0; half < CHUNK / 32 && !stop; ++half) {
+          uint32_t m32 = (uint32_t)(mask >> (32 * half));
+          while (m32) {
+            const int i = 32 * half + (int)__builtin_ctz(m32);
+            m32 &= m32 - 1u;
+            const float fi = (float)i;
+            const float ux = __builtin_fmaf(fi, sfx, fx0), uy = __builtin_fmaf(fi, sfy, fy0),
+                        uz = __builtin_fmaf(fi, sfz, fz0);
+            const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
+            const float wx = ux - flx, wy = uy - fly, wz = uz - flz;
+            const int ix = bx + (int)flx, iy = by + (int)fly, iz = bz + (int)flz;
+            const uint32_t a000 = vox_index(ix, iy, iz, mbx, mby);
+            const uint32_t dx = (ix & 3) == 3 ? dxb : 1u;
+            const uint32_t dy = (iy & 3) == 3 ? dyb : 4u;
+            const uint32_t dz = (iz & 3) == 3 ? dzb : 16u;
+            const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
+            const float v000 = load_voxel<FMT>(pool, a000, s_q, o_q), v100 = load_voxel<FMT>(pool, a000 + dx, s_q, o_q);
+            const float v010 = load_voxel<FMT>(pool, a010, s_q, o_q), v110 = load_voxel<FMT>(pool, a010 + dx, s_q, o_q);
+            const float v001 = load_voxel<FMT>(pool, a001, s_q, o_q), v101 = load_voxel<FMT>(pool, a001 + dx, s_q, o_q);
+            const float v011 = load_voxel<FMT>(pool, a011, s_q, o_q), v111 = load_voxel<FMT>(pool, a011 + dx, s_q, o_q);
+            const float c00 = __builtin_fmaf(wx, v100 - v000, v000);
+            const float c10 = __builtin_fmaf(wx, v110 - v010, v010);
+            const float c01 = __builtin_fmaf(wx, v101 - v001, v001);
+            const float c11 = __builtin_fmaf(wx, v111 - v011, v011);
+            const float c0 = __builtin_fmaf(wy, c10 - c00, c00);
+            const float c1 = __builtin_fmaf(wy, c11 - c01, c01);
+            const float val = __builtin_fmaf(wz, c1 - c0, c0);
+            float xt = __builtin_fmaf(val, tf_scale, tf_bias);
+            xt = fminf(fmaxf(xt, 0.0f), kmax_f);
+            const int it = min((int)xt, K - 2);
+            const float ft = xt - (float)it;
+            // table entry and its difference to the next entry
+            float4 q0, dq;
+            if (TF_LDS) {
+              q0 = s_tab[2 * it];
+              dq = s_tab[2 * it + 1];
+            } else {
+              q0 = gtab[it];
+              const float4 q1 = gtab[it + 1];
+              dq = make_float4(q1.x - q0.x, q1.y - q0.y, q1.z - q0.z, q1.w - q0.w);
+            }
+            const float om = 1.0f - acc.w;
+            acc.x = __builtin_fmaf(om, __builtin_fmaf(ft, dq.x, q0.x), acc.x);
+            acc.y = __builtin_fmaf(om, __builtin_fmaf(ft, dq.y, q0.y), acc.y);
+            acc.z = __builtin_fmaf(om, __builtin_fmaf(ft, dq.z, q0.z), acc.z);
+            acc.w = __builtin_fmaf(om, __builtin_fmaf(ft, dq.w, q0.w), acc.w);
+            ++evaluated;
+            if (acc.w >= tau) {
+              used = k + i + 1;
+              stop = true;
+              break;
+            }
+          }
           }
         }
         if (stop) break;
