@@ -273,20 +273,58 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   }
 }
 
-__global__ __launch_bounds__(64) void composite_kernel(BcFramePtrs f, float4* __restrict__ out) {
+// One workgroup per 4x4 block of screen tiles (16 waves, one tile each).  The
+// workgroup first culls the view's visibility order down to the bricks whose
+// rectangle meets the block (order kept, in LDS), so each wave folds only the
+// sub-images that can cover its tile.
+constexpr int kCompBlock = 4;
+__global__ __launch_bounds__(1024) void composite_kernel(BcFramePtrs f, float4* __restrict__ out) {
+  __shared__ int32_t list[BC_MAX_BRICKS];
+  __shared__ int32_t wave_count[16];
+  __shared__ int32_t n_list;
   if (f.fin->conditional && !f.ctr->fallback) return;
   const int v = blockIdx.z;
-  const int tx = blockIdx.x, ty = blockIdx.y;
-  const int ts = f.fin->tile_stride, tox = f.fin->tile_ox, toy = f.fin->tile_oy;
-  if (tx % ts != tox || ty % ts != toy) return;
-  const int lane = threadIdx.x;
   const int nb = f.n_bricks, nv = f.n_views;
   const int W = f.width, H = f.height;
+  const int ts = f.fin->tile_stride, tox = f.fin->tile_ox, toy = f.fin->tile_oy;
+  const int bx0 = blockIdx.x * kCompBlock, by0 = blockIdx.y * kCompBlock;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // ordered compaction of the bricks whose rectangle meets this block of tiles
+  if (tid == 0) n_list = 0;
+  __syncthreads();
+  for (int base = 0; base < nb; base += 1024) {
+    const int k = base + tid;
+    bool keep = false;
+    int b = 0;
+    if (k < nb) {
+      b = f.order[v * nb + k];
+      const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
+      keep = r[0] < bx0 + kCompBlock && r[2] > bx0 && r[1] < by0 + kCompBlock && r[3] > by0;
+    }
+    const uint64_t bal = __ballot(keep);
+    if (lane == 0) wave_count[wave] = __popcll(bal);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wave_count[w];
+    if (keep) list[n_list + before + __popcll(bal & ((1ull << lane) - 1ull))] = b;
+    __syncthreads();
+    if (tid == 0) {
+      int t = 0;
+      for (int w = 0; w < 16; ++w) t += wave_count[w];
+      n_list += t;
+    }
+    __syncthreads();
+  }
+  const int tx = bx0 + (wave % kCompBlock), ty = by0 + (wave / kCompBlock);
+  const int tiles_x = (W + BC_TILE - 1) / BC_TILE, tiles_y = (H + BC_TILE - 1) / BC_TILE;
+  if (tx >= tiles_x || ty >= tiles_y) return;
+  if (tx % ts != tox || ty % ts != toy) return;
   const int px = tx * BC_TILE + (lane & (BC_TILE - 1));
   const int py = ty * BC_TILE + (lane / BC_TILE);
   float4 F = make_float4(0.f, 0.f, 0.f, 0.f);
-  for (int k = 0; k < nb; ++k) {
-    const int b = f.order[v * nb + k];
+  const int n = n_list;
+  for (int k = 0; k < n; ++k) {
+    const int b = list[k];
     const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
     if (tx < r[0] || tx >= r[2] || ty < r[1] || ty >= r[3]) continue;
     const int fx = sel_first(r[0], ts, tox), fy = sel_first(r[1], ts, toy);
@@ -365,7 +403,8 @@ hipError_t bc_launch_psnr(const BcFramePtrs& f, const float4* ref, const float4*
 }
 
 hipError_t bc_launch_composite(const BcFramePtrs& f, float4* out, hipStream_t st) {
-  dim3 grid((f.width + BC_TILE - 1) / BC_TILE, (f.height + BC_TILE - 1) / BC_TILE, f.n_views);
-  composite_kernel<<<grid, 64, 0, st>>>(f, out);
+  const int tiles_x = (f.width + BC_TILE - 1) / BC_TILE, tiles_y = (f.height + BC_TILE - 1) / BC_TILE;
+  dim3 grid((tiles_x + kCompBlock - 1) / kCompBlock, (tiles_y + kCompBlock - 1) / kCompBlock, f.n_views);
+  composite_kernel<<<grid, 1024, 0, st>>>(f, out);
   return hipGetLastError();
 }
