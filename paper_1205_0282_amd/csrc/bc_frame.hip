@@ -76,6 +76,9 @@ __device__ void view_params(const BcViewIn& in, BcViewParams& vp) {
   vp.tiles_x = (in.width + BC_TILE - 1) / BC_TILE;
   vp.tiles_y = (in.height + BC_TILE - 1) / BC_TILE;
   split(in.step, vp.dt_hi, vp.dt_lo);
+  split(1.0 / in.step, vp.idt_hi, vp.idt_lo);
+  split(1.0 / (double)in.width, vp.iw_hi, vp.iw_lo);
+  split(1.0 / (double)in.height, vp.ih_hi, vp.ih_lo);
   vp.tau = (float)in.tau;
   // eye e_a = -((R0a t0 + R1a t1) + R2a t2), without fused multiply-add
   double e[3], dir[3];

@@ -169,12 +169,12 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs a) {
 // ------------------------------------------------------------------ rays
 __device__ __forceinline__ df dfv(float hi, float lo) { return df_make(hi, lo); }
 
-// smallest j >= 0 with t_in + (j + 1/2) dt >= t
-__device__ __forceinline__ int first_index(df t_in, df dt, df t) {
-  const df q = df_div(df_sub(t, t_in), dt);
+// smallest j >= 0 with t_in + (j + 1/2) dt >= t (estimate with 1/dt, then an
+// exact fix-up against the sample-time formula)
+__device__ __forceinline__ int first_index(df t_in, df dt, df idt, df t) {
+  const df q = df_mul(df_sub(t, t_in), idt);
   float jf = ceilf(df_to_f(q) - 0.5f);
   int j = (int)fmaxf(jf, 0.0f);
-  // exact fix-up against the sample-time formula
   for (int it = 0; it < 3; ++it) {
     const df tj = df_add(t_in, df_mul(df_from((float)j + 0.5f), dt));
     if (df_lt(tj, t)) { ++j; continue; }
@@ -189,7 +189,8 @@ __device__ __forceinline__ int first_index(df t_in, df dt, df t) {
 
 struct Slab { df t0, t1; bool miss; };
 
-__device__ __forceinline__ Slab slab_df(const df* o, const df* d, const float* lo, const float* hi) {
+// slab test with the reciprocal direction (id[a] valid where d[a] != 0)
+__device__ __forceinline__ Slab slab_df(const df* o, const df* d, const df* id, const float* lo, const float* hi) {
   Slab s;
   s.t0 = df_from(-INFINITY);
   s.t1 = df_from(INFINITY);
@@ -200,8 +201,8 @@ __device__ __forceinline__ Slab slab_df(const df* o, const df* d, const float* l
       if (!in) s.miss = true;
       continue;
     }
-    const df ta = df_div(df_sub(df_from(lo[a]), o[a]), d[a]);
-    const df tb = df_div(df_sub(df_from(hi[a]), o[a]), d[a]);
+    const df ta = df_mul(df_sub(df_from(lo[a]), o[a]), id[a]);
+    const df tb = df_mul(df_sub(df_from(hi[a]), o[a]), id[a]);
     s.t0 = df_max(s.t0, df_min(ta, tb));
     s.t1 = df_min(s.t1, df_max(ta, tb));
   }
@@ -224,9 +225,9 @@ struct RaySeg {
 __device__ bool ray_segment(const BcViewParams& vp, const int32_t* gdims, const BcBrick& br, int px, int py,
                             RaySeg& seg) {
   const int W = vp.width, H = vp.height;
-  const df x = df_div(df_from((float)(2 * px + 1 - W)), df_from((float)W));
-  const df y = df_div(df_from((float)(H - 2 * py - 1)), df_from((float)H));
-  df o[3], d[3];
+  const df x = df_mul(df_from((float)(2 * px + 1 - W)), dfv(vp.iw_hi, vp.iw_lo));
+  const df y = df_mul(df_from((float)(H - 2 * py - 1)), dfv(vp.ih_hi, vp.ih_lo));
+  df o[3], d[3], id[3];
   if (vp.kind == 0) {
     df u[3];
     for (int a = 0; a < 3; ++a) {
@@ -235,7 +236,8 @@ __device__ bool ray_segment(const BcViewParams& vp, const int32_t* gdims, const 
                     dfv(vp.c_hi[a], vp.c_lo[a]));
     }
     const df len = df_sqrt(df_add(df_add(df_mul(u[0], u[0]), df_mul(u[1], u[1])), df_mul(u[2], u[2])));
-    for (int a = 0; a < 3; ++a) d[a] = df_div(u[a], len);
+    const df ilen = df_div(df_from(1.0f), len);
+    for (int a = 0; a < 3; ++a) d[a] = df_mul(u[a], ilen);
   } else {
     for (int a = 0; a < 3; ++a) {
       o[a] = df_add(df_add(dfv(vp.e_hi[a], vp.e_lo[a]), df_mul(dfv(vp.a_hi[a], vp.a_lo[a]), x)),
@@ -243,19 +245,21 @@ __device__ bool ray_segment(const BcViewParams& vp, const int32_t* gdims, const 
       d[a] = dfv(vp.c_hi[a], vp.c_lo[a]);
     }
   }
+  for (int a = 0; a < 3; ++a)
+    id[a] = (d[a].hi == 0.0f && d[a].lo == 0.0f) ? df_from(0.0f) : df_div(df_from(1.0f), d[a]);
   const float zero3[3] = {0.0f, 0.0f, 0.0f};
   const float N3[3] = {(float)gdims[0], (float)gdims[1], (float)gdims[2]};
-  const Slab g = slab_df(o, d, zero3, N3);
+  const Slab g = slab_df(o, d, id, zero3, N3);
   const df t_in = df_max(df_from(0.0f), g.t0);
   if (g.miss || !df_lt(t_in, g.t1)) return false;
-  const df dt = dfv(vp.dt_hi, vp.dt_lo);
-  const int n = first_index(t_in, dt, g.t1);
   const float blo[3] = {(float)br.lo[0], (float)br.lo[1], (float)br.lo[2]};
   const float bhi[3] = {(float)br.hi[0], (float)br.hi[1], (float)br.hi[2]};
-  const Slab b = slab_df(o, d, blo, bhi);
+  const Slab b = slab_df(o, d, id, blo, bhi);
   if (b.miss || !df_lt(b.t0, b.t1)) return false;
-  int j0 = (b.t0.hi == -INFINITY) ? 0 : first_index(t_in, dt, b.t0);
-  int j1 = (b.t1.hi == INFINITY) ? n : first_index(t_in, dt, b.t1);
+  const df dt = dfv(vp.dt_hi, vp.dt_lo), idt = dfv(vp.idt_hi, vp.idt_lo);
+  const int n = first_index(t_in, dt, idt, g.t1);
+  int j0 = (b.t0.hi == -INFINITY) ? 0 : first_index(t_in, dt, idt, b.t0);
+  int j1 = (b.t1.hi == INFINITY) ? n : first_index(t_in, dt, idt, b.t1);
   j0 = min(j0, n);
   j1 = min(max(j1, j0), n);
   if (j1 <= j0) return false;

@@ -41,6 +41,9 @@ struct BcViewParams {
   int32_t width, height, tiles_x, tiles_y;
   int32_t pad0;
   float dt_hi, dt_lo;        // step (double-float)
+  float idt_hi, idt_lo;      // 1 / step
+  float iw_hi, iw_lo;        // 1 / width
+  float ih_hi, ih_lo;        // 1 / height
   float tau;
   float pad1;
   // perspective: e = eye, a/b/c: unnormalised direction u(x, y) = a x + b y + c
