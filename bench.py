@@ -77,6 +77,8 @@ def parse():
     p.add_argument("--psnr-threshold", type=float, default=40.0)
     p.add_argument("--graph", action="store_true", help="replay captured HIP graphs for the timed frames")
     p.add_argument("--autotune", action="store_true", help="pick the launch shape by timing candidates first")
+    p.add_argument("--repeats", type=int, default=10,
+                   help="frames per orbit angle for the median/p75 statistic (0 skips it)")
     p.add_argument("--frames", type=int, default=ORBIT,
                    help="distinct orbit frames cycled through (the first N of the 64-frame orbit)")
     p.add_argument("--check-pixels", type=int, default=1024,
@@ -342,6 +344,21 @@ def main():
     bc.enable_timing(False)
     assert n_timed == args.steps, (n_timed, args.steps)
 
+    # the paper's statistic (untimed by the contract above): median of 10
+    # frames per orbit angle, 75th percentile over the angles
+    paper_stat = None
+    if args.repeats > 0:
+        bc.enable_timing(True)
+        for i in range(nf):
+            bc.set_views(sets[i])
+            for _ in range(args.repeats):
+                bc.render(out)
+        ft = np.asarray(bc.frame_times(), np.float64).reshape(nf, args.repeats)
+        bc.enable_timing(False)
+        med = np.median(ft, axis=1)
+        paper_stat = {"median_of": args.repeats, "p75_over_angles_ms": float(np.percentile(med, 75)),
+                      "mean_ms": float(ft.mean()), "angles": nf}
+
     idx = [i % nf for i in range(args.steps)]
     tot_samples = float(sum(samples[i] for i in idx))
     tot_bytes = float(sum(algo_bytes[i] for i in idx))
@@ -377,6 +394,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "render_kernel", "algo_bytes_per_launch": tot_bytes / args.steps},
+        "paper_statistic": paper_stat,
         "precision_vs_oracle": precision,
         "learned": learned,
         "cpu_baseline": cpu,

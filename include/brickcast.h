@@ -218,6 +218,10 @@ int bc_autotune(bc_ctx* ctx, float* out, void* stream, int frames, int64_t chose
  * BC_E_ARG for a null ms_out. */
 int bc_enable_timing(bc_ctx* ctx, int enable);
 int bc_get_timing(bc_ctx* ctx, double ms_out[3], int* n_frames);
+/* Whole-frame milliseconds (first event to last) of each frame of the current
+ * timing window, in order, at most cap of them; *n_frames (may be NULL)
+ * receives the window's frame count.  Waits for the last frame. */
+int bc_get_frame_times(bc_ctx* ctx, double* ms, int cap, int* n_frames);
 
 /* Brick table after bc_load_bricks: per brick the core box lo/hi (6 int32,
  * global voxel coordinates) and the FP8 (scale, offset) (1, 0 otherwise),

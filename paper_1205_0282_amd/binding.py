@@ -25,7 +25,7 @@ EXPORTS = [
     "bc_get_bricks", "bc_get_visibility_order", "bc_get_rects", "bc_read_brick",
     "bc_enable_timing", "bc_get_timing", "bc_set_option",
     "bc_cnn_plan", "bc_cnn_bind", "bc_cnn_set_weights", "bc_cnn_get_weights", "bc_cnn_forward",
-    "bc_cnn_gradients", "bc_cnn_train_step", "bc_set_learned", "bc_autotune",
+    "bc_cnn_gradients", "bc_cnn_train_step", "bc_set_learned", "bc_autotune", "bc_get_frame_times",
 ]
 CNN_N_PARAMS = 15056
 BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS, BC_OPT_SAMPLE_CHUNK, BC_OPT_GRAPH = 0, 1, 2, 3
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "bc_cnn_plan": (I, [P, I, I, I, C.POINTER(C.c_size_t)]),
         "bc_set_learned": (I, [P, I, D, D, I]),
         "bc_autotune": (I, [P, P, P, I, C.POINTER(C.c_int64)]),
+        "bc_get_frame_times": (I, [P, C.POINTER(C.c_double), I, C.POINTER(I)]),
         "bc_cnn_bind": (I, [P, P, C.c_size_t]),
         "bc_cnn_set_weights": (I, [P, C.POINTER(F), C.POINTER(F), C.POINTER(F), C.c_size_t, I64]),
         "bc_cnn_get_weights": (I, [P, C.POINTER(F), C.POINTER(F), C.POINTER(F), C.c_size_t, C.POINTER(I64)]),
@@ -307,6 +308,13 @@ class BrickCaster:
                                                n, h, w, float(lr), C.byref(loss) if want_loss else None,
                                                C.c_void_p(st)))
         return float(loss.value) if want_loss else None
+
+    def frame_times(self, cap=4096):
+        """Whole-frame ms of every frame timed since enable_timing."""
+        ms = (C.c_double * cap)()
+        n = C.c_int()
+        self._check(self.lib.bc_get_frame_times(self.h, ms, cap, C.byref(n)))
+        return [float(ms[i]) for i in range(min(cap, n.value))]
 
     def bricks(self):
         n = C.c_int()

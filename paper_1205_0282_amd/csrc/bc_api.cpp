@@ -987,6 +987,24 @@ int bc_get_timing(bc_ctx* c, double ms_out[3], int* n_frames) {
   return BC_OK;
 }
 
+int bc_get_frame_times(bc_ctx* c, double* ms, int cap, int* n_frames) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (!ms && cap > 0) return fail(c, BC_E_ARG, "bc_get_frame_times: ms is NULL");
+  if (c->device < 0) return fail(c, BC_E_STATE, "bc_get_frame_times: host-only context");
+  HIPCHECK(c, hipSetDevice(c->device));
+  int r = wait_frame(c);
+  if (r) return r;
+  const int n = std::min(cap, c->timed_frames);
+  for (int k = 0; k < n; ++k) {
+    float t = 0.0f;
+    HIPCHECK(c, hipEventElapsedTime(&t, c->tev[4 * (size_t)k], c->tev[4 * (size_t)k + 3]));
+    ms[k] = t;
+  }
+  if (n_frames) *n_frames = c->timed_frames;
+  return BC_OK;
+}
+
 int bc_get_bricks(bc_ctx* c, int32_t* lo_hi, float* so, float* mm, int cap, int* n) {
   if (!c) return BC_E_ARG;
   c->err.clear();
