@@ -182,7 +182,7 @@ int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);
  *    to 0).  The per-cell classification is recomputed on the device whenever
  *    the opacity-corrected table changes.
  *  BC_OPT_RENDER_WORKGROUPS: workgroups (256 threads) of the persistent
- *    ray-casting launch; default 8 per compute unit.
+ *    ray-casting launch; default 4 per compute unit.
  *  BC_OPT_SAMPLE_CHUNK (32 or 64, default 32): samples per ray whose
  *    occupancy is gathered before the occupied ones are evaluated.  Images do
  *    not depend on it.

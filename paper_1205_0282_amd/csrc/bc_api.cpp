@@ -370,7 +370,7 @@ int bc_create(int hip_device, bc_ctx** out) {
       return BC_E_HIP;
     }
     c->n_cu = prop.multiProcessorCount;
-    c->render_workgroups = c->n_cu * 8;
+    c->render_workgroups = c->n_cu * 4;
     bool ok = true;
     for (int i = 0; i < 2 && ok; ++i) {
       ok = hipHostMalloc(reinterpret_cast<void**>(&c->pinned[i]), sizeof(BcFrameIn) * kPasses, hipHostMallocDefault) ==

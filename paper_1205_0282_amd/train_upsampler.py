@@ -186,7 +186,7 @@ def main():
     np.save(a.out, w, allow_pickle=False)
     summary = {"pairs": step, "cubes": n_cubes, "cube_edge": a.cube, "sources": n_src,
                "frame": [a.width, a.height], "coarse_step": 2.0, "fine_step": 0.5, "lr": a.lr,
-               "schedule": "cosine", "adam_steps": st, "val_cube_seed": 999, "train_cube_seeds": [1000, 999 + n_cubes + 1],
+               "schedule": "cosine", "adam_steps": st, "val_cube_seed": 999, "train_cube_seeds": f"1000..{999 + n_cubes}",
                "val_psnr_db": {"network_before": psnr0, "network_after": psnr1, "bilinear": psnr_bil},
                "loss_curve": losses, "seconds": time.perf_counter() - t0}
     with open(os.path.splitext(a.out)[0] + ".json", "w") as fh:
