@@ -76,6 +76,8 @@ def parse():
     p.add_argument("--weights", default=os.path.join(ROOT, "paper_1205_0282_amd", "weights", "upsampler.npy"))
     p.add_argument("--psnr-threshold", type=float, default=40.0)
     p.add_argument("--graph", action="store_true", help="replay captured HIP graphs for the timed frames")
+    p.add_argument("--xcd-queues", type=int, choices=(0, 1), default=1,
+                   help="1: one work queue of whole bricks per XCD (default); 0: a single queue")
     p.add_argument("--autotune", action="store_true", help="pick the launch shape by timing candidates first")
     p.add_argument("--repeats", type=int, default=10,
                    help="frames per orbit angle for the median/p75 statistic (0 skips it)")
@@ -268,6 +270,7 @@ def main():
     bc.plan(recipe.dims, (brick,) * 3, storage=args.storage, src_dtype=src_dtype, max_views=per_launch,
             max_w=W, max_h=H)
     bc.bind()
+    bc.set_option(binding.BC_OPT_XCD_QUEUES, args.xcd_queues)
     t = time.perf_counter()
     src = torch.from_numpy(vol).to(dev)
     bc.load(src)
@@ -386,7 +389,7 @@ def main():
         "config": {"workload": args.workload, "cube": list(recipe.dims), "brick": brick,
                    "image": [W, H], "step_vox": 0.5, "ert": 0.99, "storage": args.storage,
                    "orbit_frames": nf * per_launch, "views_per_launch": per_launch,
-                   "graph": bool(args.graph), "autotuned": tuned},
+                   "graph": bool(args.graph), "autotuned": tuned, "xcd_queues": args.xcd_queues},
         "stage_ms_per_frame": {"setup": stage_ms[0] / n_timed, "render": stage_ms[1] / n_timed,
                                "composite": stage_ms[2] / n_timed},
         "samples_per_frame": tot_samples / args.steps,

@@ -191,8 +191,13 @@ int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);
  *    view count, frame size, table size, launch options, mode or `out` change)
  *    and replays it; images are identical.  With a graph, timing reports the
  *    whole frame in stage 1 (ray casting) and zero for the other stages.
+ *  BC_OPT_XCD_QUEUES (default 1): 1 splits the work items into 8 queues of
+ *    whole bricks (brick b in queue b % 8), each served first by the
+ *    workgroups of one XCD, so that the eight L2 caches hold different bricks;
+ *    0 uses a single queue.  Images do not depend on it.
  * Errors: BC_E_ARG for an unknown option or a value out of range. */
-enum bc_option { BC_OPT_EMPTY_SKIP = 0, BC_OPT_RENDER_WORKGROUPS = 1, BC_OPT_SAMPLE_CHUNK = 2, BC_OPT_GRAPH = 3 };
+enum bc_option { BC_OPT_EMPTY_SKIP = 0, BC_OPT_RENDER_WORKGROUPS = 1, BC_OPT_SAMPLE_CHUNK = 2, BC_OPT_GRAPH = 3,
+                 BC_OPT_XCD_QUEUES = 4 };
 int bc_set_option(bc_ctx* ctx, int option, int64_t value);
 
 /* Autotuner: renders the current views (plain frames) with every candidate

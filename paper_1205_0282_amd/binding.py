@@ -28,7 +28,7 @@ EXPORTS = [
     "bc_cnn_gradients", "bc_cnn_train_step", "bc_set_learned", "bc_autotune", "bc_get_frame_times",
 ]
 CNN_N_PARAMS = 15056
-BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS, BC_OPT_SAMPLE_CHUNK, BC_OPT_GRAPH = 0, 1, 2, 3
+BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS, BC_OPT_SAMPLE_CHUNK, BC_OPT_GRAPH, BC_OPT_XCD_QUEUES = 0, 1, 2, 3, 4
 
 
 class LibraryMissing(RuntimeError):

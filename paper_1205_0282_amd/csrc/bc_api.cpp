@@ -22,11 +22,11 @@ namespace {
 thread_local std::string g_create_error;
 
 struct GraphKey {
-  bool learned = false, ess = false;
+  bool learned = false, ess = false, xcd = false;
   int n_views = 0, W = 0, H = 0, K = 0, chunk = 0, wgs = 0;
   const void* out = nullptr;
   bool operator==(const GraphKey& o) const {
-    return learned == o.learned && ess == o.ess && n_views == o.n_views && W == o.W && H == o.H && K == o.K &&
+    return learned == o.learned && ess == o.ess && xcd == o.xcd && n_views == o.n_views && W == o.W && H == o.H && K == o.K &&
            chunk == o.chunk && wgs == o.wgs && out == o.out;
   }
 };
@@ -57,7 +57,7 @@ struct bc_ctx {
   size_t elem_bytes = 4, src_elem_bytes = 4;
   size_t bytes[4] = {0, 0, 0, 0};
   size_t off_bricks = 0, off_fin = 0, off_views = 0, off_order = 0, off_rects = 0, off_item_base = 0,
-         off_ctr = 0, off_occ = 0;
+         off_ctr = 0, off_occ = 0, off_item_perm = 0;
   int max_occ_words = 0;
   void* dev[4] = {nullptr, nullptr, nullptr, nullptr};
   // per-frame input ring (pinned host memory, kPasses pass inputs per slot) and events
@@ -79,6 +79,7 @@ struct bc_ctx {
   // kernel launch shape and options
   int render_workgroups = 0;
   bool ess = true;
+  bool xcd_queues = true;
   int chunk = 32;
   // captured frames (one per input slot)
   bool use_graph = false;
@@ -228,6 +229,8 @@ BcFramePtrs frame_ptrs(bc_ctx* c) {
   f.order = reinterpret_cast<int32_t*>(meta + c->off_order);
   f.rects = reinterpret_cast<int32_t*>(meta + c->off_rects);
   f.item_base = reinterpret_cast<int32_t*>(meta + c->off_item_base);
+  f.item_perm = reinterpret_cast<int32_t*>(meta + c->off_item_perm);
+  f.n_queues = c->xcd_queues ? 8 : 1;
   f.ctr = reinterpret_cast<BcCounters*>(meta + c->off_ctr);
   f.sub = static_cast<float4*>(c->dev[2]);
   f.pool = c->dev[0];
@@ -497,6 +500,7 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
   c->off_order = m; m = align256(m + sizeof(int32_t) * BC_MAX_VIEWS * c->n_bricks);
   c->off_rects = m; m = align256(m + sizeof(int32_t) * 4 * BC_MAX_VIEWS * c->n_bricks);
   c->off_item_base = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
+  c->off_item_perm = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
   c->off_ctr = m; m = align256(m + sizeof(BcCounters));
   c->off_occ = m; m = align256(m + sizeof(uint32_t) * (size_t)occ_words);
   c->bytes[1] = m;
@@ -796,6 +800,7 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     key.chunk = c->chunk;
     key.ess = c->ess;
     key.wgs = c->render_workgroups;
+    key.xcd = c->xcd_queues;
     key.out = out;
     GraphSlot& g = c->graphs[slot];
     if (!g.exec || !(g.key == key)) {
@@ -882,6 +887,10 @@ int bc_set_option(bc_ctx* c, int option, int64_t value) {
     case BC_OPT_SAMPLE_CHUNK:
       if (value != 32 && value != 64) return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_SAMPLE_CHUNK takes 32 or 64");
       c->chunk = (int)value;
+      return BC_OK;
+    case BC_OPT_XCD_QUEUES:
+      if (value != 0 && value != 1) return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_XCD_QUEUES takes 0 or 1");
+      c->xcd_queues = value != 0;
       return BC_OK;
     case BC_OPT_GRAPH:
       if (value != 0 && value != 1) return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_GRAPH takes 0 or 1");

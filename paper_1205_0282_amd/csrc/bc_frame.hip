@@ -234,18 +234,25 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
     for (int b = tid; b < nb; b += blockDim.x) brick_rect(vp, f.bricks[b], f.rects + ((int64_t)v * nb + b) * 4);
     __syncthreads();
   }
-  // work items, brick-major: entry k = b * nv + v owns the selected tiles of
-  // its rectangle; a conditional pass without the fall-back flag has none
+  // work items: entry (b, v) owns the selected tiles of its rectangle (none in
+  // a conditional pass without the fall-back flag).  Entries are numbered in
+  // queue order -- bricks grouped by b % Q -- so that queue q (served first by
+  // the waves of XCD q) holds whole bricks and the XCDs' L2 caches hold
+  // different bricks.
   const bool skip = f.fin->conditional && !f.ctr->fallback;
   const int ts = f.fin->tile_stride, tox = f.fin->tile_ox, toy = f.fin->tile_oy;
+  const int Q = f.n_queues;
   const int K = nb * nv;
   const int seg = (K + blockDim.x - 1) / blockDim.x;
   const int k0 = tid * seg, k1 = min(k0 + seg, K);
+  auto count_at = [&](int pos) -> int32_t {
+    int b, v;
+    queue_entry(pos, nb, nv, Q, b, v);
+    const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
+    return skip ? 0 : sel_count(r[0], r[2], ts, tox) * sel_count(r[1], r[3], ts, toy);
+  };
   int32_t sum = 0;
-  for (int k = k0; k < k1; ++k) {
-    const int32_t* r = f.rects + ((int64_t)(k % nv) * nb + k / nv) * 4;
-    sum += skip ? 0 : sel_count(r[0], r[2], ts, tox) * sel_count(r[1], r[3], ts, toy);
-  }
+  for (int k = k0; k < k1; ++k) sum += count_at(k);
   spart[tid] = sum;
   __syncthreads();
   if (tid == 0) {
@@ -255,6 +262,7 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
       spart[i] = run;
       run += t;
     }
+    f.item_perm[K] = run;
     f.item_base[K] = run;
     const uint32_t n_items = (uint32_t)min((int64_t)run, f.max_items);
     f.ctr->n_items = n_items;
@@ -270,9 +278,22 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   __syncthreads();
   int32_t run = spart[tid];
   for (int k = k0; k < k1; ++k) {
-    f.item_base[k] = run;
-    const int32_t* r = f.rects + ((int64_t)(k % nv) * nb + k / nv) * 4;
-    run += skip ? 0 : sel_count(r[0], r[2], ts, tox) * sel_count(r[1], r[3], ts, toy);
+    f.item_perm[k] = run;
+    int b, v;
+    queue_entry(k, nb, nv, Q, b, v);
+    f.item_base[b * nv + v] = run;
+    run += count_at(k);
+  }
+  __syncthreads();
+  if (tid < 8) {
+    f.ctr->qnext[tid] = 0u;
+    int g0 = 0;
+    for (int g = 0; g < min(tid, Q); ++g) g0 += group_size(nb, Q, g);
+    f.ctr->qbound[tid] = tid < Q ? (uint32_t)f.item_perm[g0 * nv] : (uint32_t)f.item_perm[K];
+  }
+  if (tid == 8) {
+    f.ctr->qbound[8] = (uint32_t)f.item_perm[K];
+    f.ctr->n_queues = (uint32_t)Q;
   }
 }
 

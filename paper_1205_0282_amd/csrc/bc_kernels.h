@@ -26,13 +26,15 @@ struct BcFramePtrs {
   const BcBrick* bricks;
   int32_t* order;         // [BC_MAX_VIEWS][n_bricks]
   int32_t* rects;         // [BC_MAX_VIEWS][n_bricks][4] tiles (x0, y0, x1, y1)
-  int32_t* item_base;     // [n_bricks * n_views + 1]
+  int32_t* item_base;     // [n_bricks * n_views + 1] first item of entry b * n_views + v
+  int32_t* item_perm;     // [n_bricks * n_views + 1] first item of the entry at each queue-order position
   BcCounters* ctr;
   float4* sub;            // sub-image tiles: [max_items][64]
   const void* pool;
   uint32_t* occ;          // cell-occupancy bits of every brick
   int32_t ess;            // skip samples in clear cells
   int32_t chunk;          // samples per occupancy-mask chunk of the ray caster (32 or 64)
+  int32_t n_queues;       // 8: bricks split over one work queue per XCD; 1: one queue
   int32_t K;              // transfer-function entries
   int32_t n_bricks, n_views;
   int32_t gdims[3];
@@ -46,6 +48,28 @@ hipError_t bc_launch_classify(const BcFramePtrs& f, int max_words, hipStream_t s
 hipError_t bc_launch_render(const BcFramePtrs& f, int n_workgroups, hipStream_t st);
 hipError_t bc_launch_composite(const BcFramePtrs& f, float4* out, hipStream_t st);
 hipError_t bc_launch_psnr(const BcFramePtrs& f, const float4* ref, const float4* img, hipStream_t st);
+
+// Queue order of the (brick, view) entries: bricks grouped by b % Q, then b,
+// then view.  Returns the position of entry (b, v) and, inversely, the entry at
+// a position.
+__device__ __forceinline__ int group_size(int nb, int Q, int x) { return x < nb ? (nb - x + Q - 1) / Q : 0; }
+__device__ __forceinline__ int queue_pos(int b, int v, int nb, int nv, int Q) {
+  const int x = b % Q;
+  int before = 0;
+  for (int g = 0; g < x; ++g) before += group_size(nb, Q, g);
+  return (before + b / Q) * nv + v;
+}
+__device__ __forceinline__ void queue_entry(int pos, int nb, int nv, int Q, int& b, int& v) {
+  const int e = pos / nv;
+  v = pos % nv;
+  int cum = 0, x = 0;
+  for (; x < Q - 1; ++x) {
+    const int g = group_size(nb, Q, x);
+    if (e < cum + g) break;
+    cum += g;
+  }
+  b = x + (e - cum) * Q;
+}
 
 // tile selection {t : t % s == o}: first selected tile >= lo, count in [lo, hi)
 __device__ __forceinline__ int sel_first(int lo, int s, int o) { return lo + ((o - lo) % s + s) % s; }

@@ -303,20 +303,36 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
   const int ts = fin->tile_stride, tox = fin->tile_ox, toy = fin->tile_oy;
   constexpr uint32_t esz = FMT == 0 ? 4 : (FMT == 1 ? 2 : 1);
   uint64_t nominal = 0, evaluated = 0;
+  // queue of this workgroup's XCD first (workgroups are dispatched to the
+  // XCDs round robin), then the others once it is drained
+  const int Q = (int)f.ctr->n_queues;
+  int q = (int)(blockIdx.x % (unsigned)Q), drained = 0;
   for (;;) {
     uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(&f.ctr->queue, 1u);
-    item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
-    if (item >= n_items) break;
+    bool have = false;
+    while (drained < Q) {
+      uint32_t it = 0;
+      if (lane == 0) it = f.ctr->qbound[q] + atomicAdd(&f.ctr->qnext[q], 1u);
+      it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+      if (it < f.ctr->qbound[q + 1] && it < n_items) {
+        item = it;
+        have = true;
+        break;
+      }
+      ++drained;
+      q = (q + 1 == Q) ? 0 : q + 1;
+    }
+    if (!have) break;
     int lo = 0, hi = KB;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if ((uint32_t)f.item_base[mid] <= item) lo = mid; else hi = mid;
+      if ((uint32_t)f.item_perm[mid] <= item) lo = mid; else hi = mid;
     }
-    const int b = lo / nv, v = lo % nv;
+    int b, v;
+    queue_entry(lo, nb, nv, Q, b, v);
     const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
     const int cx = sel_count(r[0], r[2], ts, tox);
-    const int local = (int)(item - (uint32_t)f.item_base[lo]);
+    const int local = (int)(item - (uint32_t)f.item_perm[lo]);
     const int tx = sel_first(r[0], ts, tox) + (local % cx) * ts, ty = sel_first(r[1], ts, toy) + (local / cx) * ts;
     const int px = tx * BC_TILE + (lane & (BC_TILE - 1));
     const int py = ty * BC_TILE + (lane / BC_TILE);

@@ -78,6 +78,9 @@ struct BcCounters {
   uint32_t fallback;         // learned frame: validation PSNR below threshold
   float psnr_db;             // learned frame: PSNR of the validation tiles
   uint32_t total_items;      // work items of all passes of the frame
-  uint32_t pad_;
+  uint32_t n_queues;         // work queues of the pass (one per XCD, or one)
+  uint32_t qnext[8];         // next item of each queue (relative to its start)
+  uint32_t qbound[9];        // queue q holds items [qbound[q], qbound[q+1])
+  uint32_t pad2_[3];
   uint32_t minmax[BC_MAX_BRICKS][2];   // load time: ordered-int min/max per brick
 };

@@ -275,3 +275,16 @@ def test_autotune_keeps_the_image(small_cube):
     again = bc.render().cpu().numpy()
     assert np.array_equal(again, img.astype(np.float32))
     bc.close()
+
+
+def test_xcd_queues_and_chunks_do_not_change_the_image(small_cube):
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    views = [synth.orbit_view(vol.shape[::-1], f, kind="persp", width=120, height=90) for f in (2, 40)]
+    ref = gpu_render(vol, (40, 48, 56), views, rgba, vmin, vmax,
+                     options={binding.BC_OPT_XCD_QUEUES: 0, binding.BC_OPT_SAMPLE_CHUNK: 32})
+    for q, ch, wg in ((1, 64, 64), (1, 32, 3), (0, 64, 1000)):
+        img = gpu_render(vol, (40, 48, 56), views, rgba, vmin, vmax,
+                         options={binding.BC_OPT_XCD_QUEUES: q, binding.BC_OPT_SAMPLE_CHUNK: ch,
+                                  binding.BC_OPT_RENDER_WORKGROUPS: wg})
+        assert np.array_equal(img, ref), (q, ch, wg)
