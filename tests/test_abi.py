@@ -191,3 +191,34 @@ def test_get_bricks_after_plan(lib, host_ctx):
     from oracle import raycast as rc_
     ref = rc_.brick_grid((70, 64, 40), (32, 32, 32))
     assert np.array_equal(lohi, np.array([list(b.lo) + list(b.hi) for b in ref], np.int32))
+
+
+def test_options_learned_mode_and_upsampler_argument_checks(lib, host_ctx):
+    ok = {binding.BC_OPT_EMPTY_SKIP: (0, 1), binding.BC_OPT_SAMPLE_CHUNK: (32, 64),
+          binding.BC_OPT_RENDER_WORKGROUPS: (1, 4096), binding.BC_OPT_XCD_QUEUES: (0, 1)}
+    bad = {binding.BC_OPT_EMPTY_SKIP: (2, -1), binding.BC_OPT_SAMPLE_CHUNK: (16, 0),
+           binding.BC_OPT_RENDER_WORKGROUPS: (0, 1 << 21), binding.BC_OPT_XCD_QUEUES: (2,),
+           binding.BC_OPT_GRAPH: (5,), 99: (1,)}
+    for opt, vals in ok.items():
+        for v in vals:
+            assert lib.bc_set_option(host_ctx, opt, v) == binding.BC_OK, (opt, v)
+    for opt, vals in bad.items():
+        for v in vals:
+            assert lib.bc_set_option(host_ctx, opt, v) == binding.BC_E_ARG, (opt, v)
+    assert lib.bc_set_learned(host_ctx, 1, 2.0, 40.0, 8) == binding.BC_OK
+    assert lib.bc_set_learned(host_ctx, 2, 2.0, 40.0, 8) == binding.BC_E_ARG
+    assert lib.bc_set_learned(host_ctx, 1, 0.0, 40.0, 8) == binding.BC_E_ARG
+    assert lib.bc_set_learned(host_ctx, 1, 2.0, float("inf"), 8) == binding.BC_E_ARG
+    assert lib.bc_set_learned(host_ctx, 1, 2.0, 40.0, 65) == binding.BC_E_ARG
+    nb = C.c_size_t()
+    assert lib.bc_cnn_plan(host_ctx, 0, 10, 10, C.byref(nb)) == binding.BC_E_ARG
+    assert lib.bc_cnn_plan(host_ctx, 1, 10, 9000, C.byref(nb)) == binding.BC_E_ARG
+    assert lib.bc_cnn_plan(host_ctx, 1, 10, 10, None) == binding.BC_E_ARG
+    assert lib.bc_cnn_plan(host_ctx, 2, 540, 960, C.byref(nb)) == binding.BC_OK and nb.value > 0
+    assert lib.bc_cnn_bind(host_ctx, C.c_void_p(256), nb.value) == binding.BC_E_STATE      # host-only
+    w = np.zeros(binding.CNN_N_PARAMS, np.float32)
+    assert lib.bc_cnn_set_weights(host_ctx, w.ctypes.data_as(C.POINTER(C.c_float)), None, None, w.size,
+                                  0) == binding.BC_E_STATE
+    assert lib.bc_autotune(host_ctx, None, None, 2, None) == binding.BC_E_STATE
+    ms = (C.c_double * 3)()
+    assert lib.bc_get_timing(host_ctx, ms, None) == binding.BC_E_STATE
