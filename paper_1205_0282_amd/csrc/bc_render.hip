@@ -85,6 +85,15 @@ __device__ __forceinline__ uint32_t vox_index(int x, int y, int z, int mbx, int 
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// a * b + c on the low 24 bits of a and b (one full-rate instruction; the
+// compiler cannot prove the operands fit 24 bits and would otherwise emit a
+// 64-bit multiply-add)
+__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t d;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
 // ------------------------------------------------------------------ classify
 struct ClassifyArgs {
   const BcBrick* bricks;
@@ -278,7 +287,7 @@ __device__ __forceinline__ float frac32(int64_t v) { return (float)(uint32_t)v *
 
 // ------------------------------------------------------------------ render
 template <int FMT, bool TF_LDS, int CHUNK>
-__global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
+__global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   // table entry k at 2k, its difference to entry k+1 at 2k+1
   __shared__ float4 s_tab[TF_LDS ? 2 * BC_TF_LDS : 2];
   const int lane = threadIdx.x & 63;
@@ -344,7 +353,7 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
       const float tau = vp.tau;
       const int cmx = br.hi[0] - br.lo[0], cmy = br.hi[1] - br.lo[1], cmz = br.hi[2] - br.lo[2];
       const int mbx = br.mb[0], mby = br.mb[1];
-      const uint32_t WX = (uint32_t)br.occ_w[0], WY = (uint32_t)br.occ_w[1];
+      const uint32_t WX = (uint32_t)br.occ_w[0], WY = (uint32_t)br.occ_w[1], WX4 = 4u * WX;
       const uint32_t n_occ = WX * WY * (uint32_t)br.occ_w[2];
       const __amdgpu_buffer_rsrc_t occ = make_rsrc(f.occ + br.occ_offset, n_occ * 4u);
       const uint32_t n_vox = (uint32_t)br.gdim[0] * (uint32_t)br.gdim[1] * (uint32_t)br.gdim[2];
@@ -371,15 +380,18 @@ __global__ __launch_bounds__(256) void render_kernel(BcFramePtrs f) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
               const uint32_t ix = (uint32_t)hi32(un0), iy = (uint32_t)hi32(un1), iz = (uint32_t)hi32(un2);
-              wofs[i] = ((ix >> 2) + __umul24(WX, (iy >> 2) + __umul24(WY, iz >> 1))) * 4u;
-              bit[i] = (ix & 3u) | ((iy & 3u) << 2) | ((iz & 1u) << 4);
+              // word (ix/4, iy/4, iz/2) as a byte offset; bit (ix%4) + 4 (iy%4) + 16 (iz%2), of
+              // which the bit-field extract below reads only the low five bits
+              wofs[i] = mad_u24(mad_u24(iz >> 1, WY, iy >> 2), WX4, ix & ~3u);
+              const uint32_t bxy = (ix & 3u) | ((iy << 2) & ~3u);
+              bit[i] = (bxy & 15u) | ((iz << 4) & ~15u);
               un0 += s0; un1 += s1; un2 += s2;
             }
 #pragma unroll
             for (int i = 0; i < 16; ++i) word[i] = __builtin_amdgcn_raw_buffer_load_b32(occ, wofs[i], 0, 0);
             uint32_t mh = 0;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) mh |= ((word[i] >> bit[i]) & 1u) << i;
+            for (int i = 0; i < 16; ++i) mh |= __builtin_amdgcn_ubfe(word[i], bit[i], 1u) << i;
             m |= (uint64_t)mh << (16 * h);
           }
           mask &= m;
