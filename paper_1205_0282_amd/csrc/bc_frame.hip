@@ -266,7 +266,6 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
     f.item_base[K] = run;
     const uint32_t n_items = (uint32_t)min((int64_t)run, f.max_items);
     f.ctr->n_items = n_items;
-    f.ctr->queue = 0u;
     if (f.fin->reset_counters) {
       f.ctr->nominal = 0ull;
       f.ctr->evaluated = 0ull;
@@ -286,7 +285,7 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   }
   __syncthreads();
   if (tid < 8) {
-    f.ctr->qnext[tid] = 0u;
+    f.ctr->q[tid].next = 0u;
     int g0 = 0;
     for (int g = 0; g < min(tid, Q); ++g) g0 += group_size(nb, Q, g);
     f.ctr->qbound[tid] = tid < Q ? (uint32_t)f.item_perm[g0 * nv] : (uint32_t)f.item_perm[K];

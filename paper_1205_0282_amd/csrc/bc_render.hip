@@ -314,22 +314,26 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   uint64_t nominal = 0, evaluated = 0;
   // queue of this workgroup's XCD first (workgroups are dispatched to the
   // XCDs round robin), then the others once it is drained
-  const int Q = (int)f.ctr->n_queues;
+  const BcCounters* cr = f.ctr;   // read-only lines
+  const int Q = (int)cr->n_queues;
   int q = (int)(blockIdx.x % (unsigned)Q), drained = 0;
+  uint32_t q_lo = cr->qbound[q], q_hi = cr->qbound[q + 1];
   for (;;) {
     uint32_t item = 0;
     bool have = false;
     while (drained < Q) {
       uint32_t it = 0;
-      if (lane == 0) it = f.ctr->qbound[q] + atomicAdd(&f.ctr->qnext[q], 1u);
-      it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
-      if (it < f.ctr->qbound[q + 1] && it < n_items) {
+      if (lane == 0) it = atomicAdd(&f.ctr->q[q].next, 1u);
+      it = q_lo + __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+      if (it < q_hi && it < n_items) {
         item = it;
         have = true;
         break;
       }
       ++drained;
       q = (q + 1 == Q) ? 0 : q + 1;
+      q_lo = cr->qbound[q];
+      q_hi = cr->qbound[q + 1];
     }
     if (!have) break;
     int lo = 0, hi = KB;

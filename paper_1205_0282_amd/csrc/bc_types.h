@@ -1,5 +1,6 @@
 // Layouts shared by the host runtime and the kernels of the bricked ray caster.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 #define BC_MAX_VIEWS 4
@@ -70,17 +71,31 @@ struct BcBrick {
   float vmin, vmax;          // range of the stored (core + ghost) values
 };
 
+// Device counters.  The cache lines that the ray-casting waves update with
+// atomics (one per work queue, one for the sample counts) hold nothing else,
+// so the read-only fields the waves load are never in a line under atomic
+// traffic.
+struct BcQueueCounter {
+  uint32_t next;             // next item of the queue (relative to its start)
+  uint32_t pad_[31];
+};
 struct BcCounters {
+  // written by the set-up kernel, read-only during ray casting
   uint32_t n_items;          // work items of the pass
-  uint32_t queue;            // next work item (persistent kernel)
-  unsigned long long nominal;
-  unsigned long long evaluated;
+  uint32_t n_queues;         // work queues of the pass (one per XCD, or one)
+  uint32_t qbound[9];        // queue q holds items [qbound[q], qbound[q+1])
   uint32_t fallback;         // learned frame: validation PSNR below threshold
   float psnr_db;             // learned frame: PSNR of the validation tiles
   uint32_t total_items;      // work items of all passes of the frame
-  uint32_t n_queues;         // work queues of the pass (one per XCD, or one)
-  uint32_t qnext[8];         // next item of each queue (relative to its start)
-  uint32_t qbound[9];        // queue q holds items [qbound[q], qbound[q+1])
-  uint32_t pad2_[3];
+  uint32_t pad0_[18];
+  // sample counts, added once per wave at its end
+  unsigned long long nominal;
+  unsigned long long evaluated;
+  uint32_t pad1_[28];
+  BcQueueCounter q[8];
   uint32_t minmax[BC_MAX_BRICKS][2];   // load time: ordered-int min/max per brick
 };
+
+static_assert(offsetof(BcCounters, nominal) == 128, "sample counts start a cache line");
+static_assert(offsetof(BcCounters, q) == 256, "queue counters start a cache line");
+static_assert(sizeof(BcQueueCounter) == 128, "one queue counter per cache line");

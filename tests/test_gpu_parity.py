@@ -265,7 +265,8 @@ def test_graph_frames_match_eager_frames(small_cube):
 
 
 def test_autotune_keeps_the_image(small_cube):
-    import torch
+    """The launch shape changes only FP32 rounding inside a sample chunk (the
+    chunk size sets the base the in-chunk positions are measured from)."""
     vol = small_cube
     rgba, vmin, vmax = _ramp(vol)
     v = synth.orbit_view(vol.shape[::-1], 11, kind="persp", width=128, height=96)
@@ -273,18 +274,27 @@ def test_autotune_keeps_the_image(small_cube):
     chunk, wgs = bc.autotune(frames=2)
     assert chunk in (32, 64) and wgs > 0
     again = bc.render().cpu().numpy()
-    assert np.array_equal(again, img.astype(np.float32))
+    assert np.abs(again - img).max() <= 1e-6
     bc.close()
 
 
 def test_xcd_queues_and_chunks_do_not_change_the_image(small_cube):
+    """Work queues and workgroup counts only reorder independent work items:
+    bit-identical.  The chunk size changes FP32 rounding inside a chunk only."""
     vol = small_cube
     rgba, vmin, vmax = _ramp(vol)
     views = [synth.orbit_view(vol.shape[::-1], f, kind="persp", width=120, height=90) for f in (2, 40)]
-    ref = gpu_render(vol, (40, 48, 56), views, rgba, vmin, vmax,
-                     options={binding.BC_OPT_XCD_QUEUES: 0, binding.BC_OPT_SAMPLE_CHUNK: 32})
-    for q, ch, wg in ((1, 64, 64), (1, 32, 3), (0, 64, 1000)):
+    ref = {ch: gpu_render(vol, (40, 48, 56), views, rgba, vmin, vmax,
+                          options={binding.BC_OPT_XCD_QUEUES: 0, binding.BC_OPT_SAMPLE_CHUNK: ch})
+           for ch in (32, 64)}
+    for q, ch, wg in ((1, 64, 64), (1, 32, 3), (0, 64, 1000), (1, 32, 2000)):
         img = gpu_render(vol, (40, 48, 56), views, rgba, vmin, vmax,
                          options={binding.BC_OPT_XCD_QUEUES: q, binding.BC_OPT_SAMPLE_CHUNK: ch,
                                   binding.BC_OPT_RENDER_WORKGROUPS: wg})
-        assert np.array_equal(img, ref), (q, ch, wg)
+        assert np.array_equal(img, ref[ch]), (q, ch, wg)
+    assert np.abs(ref[32] - ref[64]).max() <= 1e-6
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    stored = rc.store_bricks(vol, rc.brick_grid(vol.shape[::-1], (40, 48, 56)))
+    res = rc.render_bricked(stored, vol.shape[::-1], cam_of(views[0]), tf, 0.5, 0.99)
+    err, _, _ = compare(ref[64][0].reshape(-1, 4), res)
+    assert err <= TOL
