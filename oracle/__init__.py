@@ -10,6 +10,10 @@ Modules:
                sampling, transfer function, front-to-back compositing with early
                ray termination, bricking with ghosts, visibility order,
                sort-last compositing (Sections 1.2, 2.1, 2.3.2, 2.3.3).
+  mip       -- maximum intensity projection (the paper's adopted operator,
+               Sections 2.3.2 and 2.3.3): per-ray maximum, any-order merge of
+               brick maxima, colour map after the merge, fixed or per-voxel
+               step.
   encoders  -- IEEE binary16 and OCP FP8 e4m3 storage encoders, per-brick
                scale/offset (no passage in the paper: storage forms of the cube).
   cnn       -- the learned upsampler's forward/backward and Adam (no passage in
