@@ -19,7 +19,12 @@ sub-image tiles written (1 KiB per 8x8 tile).  ``cpu_baseline`` is the FP64
 oracle timed on a bounded random sample of the first frame's pixels, in
 processes forked over the host cores before the GPU is touched.
 
+``--op mip`` runs the same path with maximum intensity projection (the
+paper's operator: per-ray maximum, any-order merge, colour map after the
+merge), with ``--step-policy voxel`` at one sample per voxel slice per ray.
+
     python bench.py [--gpus 1] [--steps 64] [--warmup 3] [--storage f32|f16|fp8]
+                    [--op composite|mip] [--step-policy fixed|voxel]
 """
 from __future__ import annotations
 
@@ -71,6 +76,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target wall time of the oracle sample (0 disables the CPU baseline)")
     p.add_argument("--cpu-workers", type=int, default=0, help="0 = all host cores, at most 16")
+    p.add_argument("--op", choices=("composite", "mip"), default="composite",
+                   help="ray operator: front-to-back compositing, or maximum intensity projection")
+    p.add_argument("--step-policy", choices=("fixed", "voxel"), default="fixed",
+                   help="fixed 0.5-voxel step, or one sample per voxel slice per ray (mip only)")
     p.add_argument("--learned", action="store_true",
                    help="time learned frames: coarse render + trained upsampler, validated against plain tiles")
     p.add_argument("--weights", default=os.path.join(ROOT, "paper_1205_0282_amd", "weights", "upsampler.npy"))
@@ -106,27 +115,35 @@ def view_sets(recipe, width, height, per_launch, n):
 _CPU = {}
 
 
-def _cpu_chunk(pix):
+def _oracle_render(pix):
+    """The bricked FP64 oracle of the benchmarked operator at some pixels."""
+    from oracle import mip
     from oracle import raycast as rc
     c = _CPU
+    if c["op"] == "mip":
+        step = "voxel" if c["step_policy"] == "voxel" else 0.5
+        return mip.render_mip_bricked(c["stored"], c["dims"], c["cam"], c["tf"], step, pixels=pix)
+    return rc.render_bricked(c["stored"], c["dims"], c["cam"], c["tf"], 0.5, 0.99, pixels=pix)
+
+
+def _cpu_chunk(pix):
     t0 = time.perf_counter()
-    res = rc.render_bricked(c["stored"], c["dims"], c["cam"], c["tf"], 0.5, 0.99, pixels=pix)
+    res = _oracle_render(pix)
     return int(res.samples.sum()), time.perf_counter() - t0
 
 
 def _ref_chunk(pix):
     """Oracle pixels (main result and near-tie branches) for the precision check."""
-    from oracle import raycast as rc
-    c = _CPU
-    res = rc.render_bricked(c["stored"], c["dims"], c["cam"], c["tf"], 0.5, 0.99, pixels=pix)
+    res = _oracle_render(pix)
     return res.image, {int(k): v for k, v in res.branches.items()}
 
 
-def oracle_reference(vol, recipe, brick, view, rgba, vmin, vmax, n_px, workers):
+def oracle_reference(vol, recipe, brick, view, rgba, vmin, vmax, n_px, workers, args):
     """FP64 oracle on the FP32 cube at a seeded sample of hit pixels of one frame."""
     from oracle import raycast as rc
     dims = recipe.dims
     _CPU.update(stored=rc.store_bricks(vol, rc.brick_grid(dims, (brick,) * 3)), dims=dims,
+                op=args.op, step_policy=args.step_policy,
                 cam=rc.Camera(view.modelview, view.projection, view.width, view.height),
                 tf=rc.TransferFunction(rgba, vmin, vmax))
     cam = _CPU["cam"]
@@ -159,10 +176,11 @@ def precision_report(gpu_px, ref_img, branches):
             "psnr_db": (float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)), "near_tie_rays": len(branches)}
 
 
-def cpu_baseline(vol, recipe, brick, view, rgba, vmin, vmax, seconds, workers):
+def cpu_baseline(vol, recipe, brick, view, rgba, vmin, vmax, seconds, workers, args):
     from oracle import raycast as rc
     dims = recipe.dims
     _CPU.update(stored=rc.store_bricks(vol, rc.brick_grid(dims, (brick,) * 3)), dims=dims,
+                op=args.op, step_policy=args.step_policy,
                 cam=rc.Camera(view.modelview, view.projection, view.width, view.height),
                 tf=rc.TransferFunction(rgba, vmin, vmax))
     rng = np.random.default_rng(20240601)
@@ -181,7 +199,8 @@ def cpu_baseline(vol, recipe, brick, view, rgba, vmin, vmax, seconds, workers):
     samples = sum(o[0] for o in out)
     _CPU.clear()
     return {"value": samples / wall / 1e9, "unit": "Gsamples/s", "cores": workers, "kind": "oracle",
-            "sample": f"{n_px} uniformly drawn pixels of orbit frame 0 (seeded), FP64 bricked oracle with "
+            "sample": f"{n_px} uniformly drawn pixels of orbit frame 0 (seeded), FP64 bricked "
+                      f"{'maximum-intensity' if args.op == 'mip' else 'compositing'} oracle with "
                       f"near-tie branches, {samples} samples in {wall:.1f} s over {workers} forked processes"}
 
 
@@ -236,6 +255,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     recipe, brick, W, H, per_launch, src_dtype = WORKLOADS[args.workload]
+    if args.op == "composite" and args.step_policy != "fixed":
+        sys.exit("bench.py: the per-voxel step policy needs --op mip")
+    if args.op == "mip" and args.learned:
+        sys.exit("bench.py: learned frames are composited frames; drop --learned for --op mip")
     if per_launch > 1 and (args.learned or args.check_pixels or args.cpu_seconds):
         log("batched workload: learned mode, oracle check and CPU baseline are not run")
         args.learned, args.check_pixels, args.cpu_seconds = False, 0, 0
@@ -255,11 +278,11 @@ def main():
     ref = None
     if args.check_pixels > 0:
         t = time.perf_counter()
-        ref = oracle_reference(vol, recipe, brick, views[0], rgba, vmin, vmax, args.check_pixels, workers)
+        ref = oracle_reference(vol, recipe, brick, views[0], rgba, vmin, vmax, args.check_pixels, workers, args)
         log(f"oracle reference: {len(ref[0])} pixels of frame 0 in {time.perf_counter() - t:.1f} s")
     cpu = None
     if args.cpu_seconds > 0:
-        cpu = cpu_baseline(vol, recipe, brick, views[0], rgba, vmin, vmax, args.cpu_seconds, workers)
+        cpu = cpu_baseline(vol, recipe, brick, views[0], rgba, vmin, vmax, args.cpu_seconds, workers, args)
         log(f"cpu baseline: {cpu['value'] * 1e3:.4f} Msamples/s on {cpu['cores']} processes")
 
     import torch
@@ -271,6 +294,7 @@ def main():
             max_w=W, max_h=H)
     bc.bind()
     bc.set_option(binding.BC_OPT_XCD_QUEUES, args.xcd_queues)
+    bc.set_operator(args.op, args.step_policy)
     t = time.perf_counter()
     src = torch.from_numpy(vol).to(dev)
     bc.load(src)
@@ -387,7 +411,9 @@ def main():
                   "fp8": "fp8-e4m3 storage, f32 arithmetic"}[args.storage],
         "data": "synthetic",
         "config": {"workload": args.workload, "cube": list(recipe.dims), "brick": brick,
-                   "image": [W, H], "step_vox": 0.5, "ert": 0.99, "storage": args.storage,
+                   "image": [W, H], "operator": args.op,
+                   "step_vox": "per-voxel" if args.step_policy == "voxel" else 0.5,
+                   "ert": 0.99 if args.op == "composite" else "brick maximum", "storage": args.storage,
                    "orbit_frames": nf * per_launch, "views_per_launch": per_launch,
                    "graph": bool(args.graph), "autotuned": tuned, "xcd_queues": args.xcd_queues},
         "stage_ms_per_frame": {"setup": stage_ms[0] / n_timed, "render": stage_ms[1] / n_timed,

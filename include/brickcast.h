@@ -143,8 +143,8 @@ int bc_set_view(bc_ctx* ctx, const bc_view* views, int n_views);
 
 /* Enqueue one frame on `stream` (a hipStream_t; NULL = the null stream) and
  * return.  `out`: caller-owned device buffer of n_views*height*width*4
- * float32, premultiplied RGBA, 16-byte aligned; pixels no brick covers are
- * transparent black.  Errors (detected before anything is enqueued, `out`
+ * float32, premultiplied RGBA (colour-mapped RGBA under BC_OP_MIP), 16-byte
+ * aligned; pixels no brick covers are transparent black.  Errors (detected before anything is enqueued, `out`
  * untouched): BC_E_STATE if memory, bricks, transfer function or view is
  * missing; BC_E_ARG for a null or misaligned out. */
 int bc_render_frame(bc_ctx* ctx, float* out, void* stream);
@@ -164,10 +164,39 @@ int bc_render_frame(bc_ctx* ctx, float* out, void* stream);
  * non-finite threshold, validate_stride outside [1, 64]. */
 int bc_set_learned(bc_ctx* ctx, int enable, double coarse_step, double psnr_threshold_db, int validate_stride);
 
+/* Ray operator and step policy of the next frames.
+ *  BC_OP_COMPOSITE (default): front-to-back compositing of the transfer
+ *    function's opacity-corrected premultiplied colours with early ray
+ *    termination (Section 1.2); `out` holds premultiplied RGBA.
+ *  BC_OP_MIP: maximum intensity projection, the operator the paper adopts
+ *    (Section 2.3.3): each ray keeps the largest value it samples, a ray stops
+ *    once it reaches the largest value its brick stores (the paper stops at the
+ *    global maximum, Section 2.3.2; the brick's own bound gives the same
+ *    image), the per-brick maxima merge in any order, and the colour map -- the
+ *    transfer function's K straight entries, interpolated linearly over
+ *    [vmin, vmax] and clamped, opacity and dt_ref unused -- is applied once
+ *    after the merge.  A pixel whose ray takes no sample is (0, 0, 0, 0).
+ *    The views' ert_threshold is not used.  Empty-space skipping stays exact:
+ *    a cell is skipped only if every value it can take maps to the colour
+ *    map's first entry through a leading run of equal entries.
+ *  BC_STEP_FIXED (default): the views' step.
+ *  BC_STEP_PER_VOXEL: per ray, step 1 / max_a |d_a| for the unit direction d:
+ *    consecutive samples one voxel apart along the ray's dominant axis, at
+ *    least one sample in every voxel slice the ray crosses (the discrete ray
+ *    casting of Section 2.3.2); samples stay anchored at the cube entry.  The
+ *    views' step must still be valid (> 0) and is not used.
+ * Errors: BC_E_ARG for an unknown op or step_policy; BC_E_UNSUPPORTED for
+ * BC_STEP_PER_VOXEL with BC_OP_COMPOSITE (the composited table is corrected
+ * for one step per frame).  bc_render_frame returns BC_E_UNSUPPORTED for
+ * learned frames with BC_OP_MIP. */
+enum bc_operator { BC_OP_COMPOSITE = 0, BC_OP_MIP = 1 };
+enum bc_step_policy { BC_STEP_FIXED = 0, BC_STEP_PER_VOXEL = 1 };
+int bc_set_operator(bc_ctx* ctx, int op, int step_policy);
+
 /* Statistics of the last frame; waits for it to finish. */
 typedef struct {
-  uint64_t nominal_samples;    /* samples composited, up to termination, skipped-empty ones included */
-  uint64_t evaluated_samples;  /* samples actually interpolated and looked up */
+  uint64_t nominal_samples;    /* samples taken, up to termination, skipped-empty ones included */
+  uint64_t evaluated_samples;  /* samples actually interpolated (and looked up, when compositing) */
   uint32_t n_tiles;            /* (brick, view, 8x8 tile) work items of all passes of the frame */
   int32_t fell_back;           /* learned frame: 1 if it was re-rendered plain, else 0; -1 for a plain frame */
   float psnr_db;               /* learned frame: PSNR (peak 1) of the validation tiles; NaN for a plain frame */

@@ -26,9 +26,12 @@ EXPORTS = [
     "bc_enable_timing", "bc_get_timing", "bc_set_option",
     "bc_cnn_plan", "bc_cnn_bind", "bc_cnn_set_weights", "bc_cnn_get_weights", "bc_cnn_forward",
     "bc_cnn_gradients", "bc_cnn_train_step", "bc_set_learned", "bc_autotune", "bc_get_frame_times",
+    "bc_set_operator",
 ]
 CNN_N_PARAMS = 15056
 BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS, BC_OPT_SAMPLE_CHUNK, BC_OPT_GRAPH, BC_OPT_XCD_QUEUES = 0, 1, 2, 3, 4
+BC_OP_COMPOSITE, BC_OP_MIP = 0, 1
+BC_STEP_FIXED, BC_STEP_PER_VOXEL = 0, 1
 
 
 class LibraryMissing(RuntimeError):
@@ -88,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "bc_set_option": (I, [P, I, I64]),
         "bc_cnn_plan": (I, [P, I, I, I, C.POINTER(C.c_size_t)]),
         "bc_set_learned": (I, [P, I, D, D, I]),
+        "bc_set_operator": (I, [P, I, I]),
         "bc_autotune": (I, [P, P, P, I, C.POINTER(C.c_int64)]),
         "bc_get_frame_times": (I, [P, C.POINTER(C.c_double), I, C.POINTER(I)]),
         "bc_cnn_bind": (I, [P, P, C.c_size_t]),
@@ -249,6 +253,17 @@ class BrickCaster:
         ch = (C.c_int64 * 2)()
         self._check(self.lib.bc_autotune(self.h, C.c_void_p(out.data_ptr()), C.c_void_p(st), int(frames), ch))
         return int(ch[0]), int(ch[1])
+
+    def set_operator(self, op="composite", step="fixed"):
+        """op: "composite" or "mip"; step: "fixed" (the views' step) or "voxel"
+        (one sample per voxel slice along each ray's dominant axis)."""
+        ops = {"composite": BC_OP_COMPOSITE, "mip": BC_OP_MIP}
+        steps = {"fixed": BC_STEP_FIXED, "voxel": BC_STEP_PER_VOXEL}
+        if isinstance(op, str) and op not in ops or isinstance(step, str) and step not in steps:
+            raise ValueError(f"unknown operator {op!r} or step policy {step!r}")
+        o = ops[op] if isinstance(op, str) else int(op)
+        st = steps[step] if isinstance(step, str) else int(step)
+        self._check(self.lib.bc_set_operator(self.h, o, st))
 
     def set_learned(self, enable=True, coarse_step=2.0, psnr_threshold_db=40.0, validate_stride=8):
         self._check(self.lib.bc_set_learned(self.h, 1 if enable else 0, float(coarse_step),

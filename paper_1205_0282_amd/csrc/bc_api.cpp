@@ -23,11 +23,11 @@ thread_local std::string g_create_error;
 
 struct GraphKey {
   bool learned = false, ess = false, xcd = false;
-  int n_views = 0, W = 0, H = 0, K = 0, chunk = 0, wgs = 0;
+  int n_views = 0, W = 0, H = 0, K = 0, chunk = 0, wgs = 0, op = 0, step_policy = 0;
   const void* out = nullptr;
   bool operator==(const GraphKey& o) const {
     return learned == o.learned && ess == o.ess && xcd == o.xcd && n_views == o.n_views && W == o.W && H == o.H && K == o.K &&
-           chunk == o.chunk && wgs == o.wgs && out == o.out;
+           chunk == o.chunk && wgs == o.wgs && op == o.op && step_policy == o.step_policy && out == o.out;
   }
 };
 struct GraphSlot {
@@ -81,6 +81,9 @@ struct bc_ctx {
   bool ess = true;
   bool xcd_queues = true;
   int chunk = 32;
+  // ray operator and step policy (bc_set_operator)
+  int op = BC_OP_COMPOSITE;
+  int step_policy = BC_STEP_FIXED;
   // captured frames (one per input slot)
   bool use_graph = false;
   hipStream_t capture_stream = nullptr;
@@ -238,6 +241,8 @@ BcFramePtrs frame_ptrs(bc_ctx* c) {
   f.ess = c->ess ? 1 : 0;
   f.chunk = c->chunk;
   f.K = c->K;
+  f.op = c->op;
+  f.step_policy = c->step_policy;
   f.n_bricks = c->n_bricks;
   f.n_views = c->frame_views;
   for (int a = 0; a < 3; ++a) f.gdims[a] = (int32_t)c->desc.global_dims[a];
@@ -262,8 +267,9 @@ struct PassSpec {
   bool reset, conditional;
 };
 
-// per-pass input: the views at the pass's size and step, the opacity-corrected
-// premultiplied table for that step, and the tile selection
+// per-pass input: the views at the pass's size and step, the table (opacity-
+// corrected and premultiplied for that step when compositing, the straight
+// colour map for maximum intensity projection), and the tile selection
 void fill_pass(bc_ctx* c, BcFrameIn* fin, const PassSpec& p) {
   const int n = (int)c->views.size();
   for (int i = 0; i < n; ++i) {
@@ -286,6 +292,13 @@ void fill_pass(bc_ctx* c, BcFrameIn* fin, const PassSpec& p) {
   fin->reset_counters = p.reset ? 1 : 0;
   fin->conditional = p.conditional ? 1 : 0;
   fin->psnr_threshold = (float)c->psnr_threshold;
+  fin->op = c->op;
+  fin->step_policy = c->step_policy;
+  if (c->op == BC_OP_MIP) {
+    for (int k = 0; k < c->K; ++k)
+      for (int ch = 0; ch < 4; ++ch) fin->table[k][ch] = c->tf[4 * k + ch];
+    return;
+  }
   for (int k = 0; k < c->K; ++k) {
     const double a = c->tf[4 * k + 3];
     const double ac = 1.0 - std::pow(1.0 - a, p.step / c->dt_ref);
@@ -689,6 +702,8 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     if ((W & 1) || (H & 1)) return fail(c, BC_E_ARG, "bc_render_frame: learned frames need an even width and height");
     if (n > c->cnn_max_n || W / 2 > c->cnn_max_w || H / 2 > c->cnn_max_h)
       return fail(c, BC_E_ARG, "bc_render_frame: %d views of %d x %d exceed the upsampler plan", n, W, H);
+    if (c->op != BC_OP_COMPOSITE)
+      return fail(c, BC_E_UNSUPPORTED, "bc_render_frame: learned frames are trained on composited images only");
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIPCHECK(c, hipSetDevice(c->device));
@@ -717,15 +732,23 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
   }
   const size_t fin_bytes = offsetof(BcFrameIn, table) + sizeof(float) * 4 * c->K;
   c->frame_views = n;
-  // empty-space classification depends only on which table entries are zero
-  // (and on the value-to-table mapping): redo it when that pattern changes
+  // empty-space classification depends only on which table entries matter
+  // (non-zero opacity; for maximum intensity projection, different from the
+  // first entry) and on the value-to-table mapping: redo it when that changes
   bool classify = false;
   if (c->ess) {
-    std::vector<float> key(c->K + 3);
+    std::vector<float> key(c->K + 4);
     key[0] = (float)c->K;
     key[1] = pins[0].tf_scale;
     key[2] = pins[0].tf_bias;
-    for (int k = 0; k < c->K; ++k) key[3 + k] = pins[0].table[k][3] != 0.0f ? 1.0f : 0.0f;
+    key[3] = (float)c->op;
+    const float* e0 = pins[0].table[0];
+    for (int k = 0; k < c->K; ++k) {
+      const float* e = pins[0].table[k];
+      const bool m = c->op == BC_OP_MIP ? (e[0] != e0[0] || e[1] != e0[1] || e[2] != e0[2] || e[3] != e0[3])
+                                         : e[3] != 0.0f;
+      key[4 + k] = m ? 1.0f : 0.0f;
+    }
     classify = !c->occ_valid || c->occ_table != key;
     if (classify) {
       c->occ_table = key;
@@ -801,6 +824,8 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     key.ess = c->ess;
     key.wgs = c->render_workgroups;
     key.xcd = c->xcd_queues;
+    key.op = c->op;
+    key.step_policy = c->step_policy;
     key.out = out;
     GraphSlot& g = c->graphs[slot];
     if (!g.exec || !(g.key == key)) {
@@ -853,6 +878,20 @@ int bc_set_learned(bc_ctx* c, int enable, double coarse_step, double psnr_thresh
   c->coarse_step = coarse_step;
   c->psnr_threshold = psnr_threshold_db;
   c->val_stride = validate_stride;
+  return BC_OK;
+}
+
+int bc_set_operator(bc_ctx* c, int op, int step_policy) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (op != BC_OP_COMPOSITE && op != BC_OP_MIP) return fail(c, BC_E_ARG, "bc_set_operator: unknown operator %d", op);
+  if (step_policy != BC_STEP_FIXED && step_policy != BC_STEP_PER_VOXEL)
+    return fail(c, BC_E_ARG, "bc_set_operator: unknown step policy %d", step_policy);
+  if (op == BC_OP_COMPOSITE && step_policy == BC_STEP_PER_VOXEL)
+    return fail(c, BC_E_UNSUPPORTED,
+                "bc_set_operator: compositing needs one step per frame (its table is opacity-corrected for that step)");
+  c->op = op;
+  c->step_policy = step_policy;
   return BC_OK;
 }
 

@@ -346,6 +346,35 @@ __global__ __launch_bounds__(1024) void composite_kernel(BcFramePtrs f, float4* 
   const int py = ty * BC_TILE + (lane / BC_TILE);
   float4 F = make_float4(0.f, 0.f, 0.f, 0.f);
   const int n = n_list;
+  if (f.op == 1) {
+    // maximum intensity projection: the largest brick maximum (any order),
+    // then the colour map; no sample anywhere leaves the pixel clear
+    const float* subf = reinterpret_cast<const float*>(f.sub);
+    float M = -INFINITY;
+    for (int k = 0; k < n; ++k) {
+      const int b = list[k];
+      const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
+      if (tx < r[0] || tx >= r[2] || ty < r[1] || ty >= r[3]) continue;
+      const int fx = sel_first(r[0], ts, tox), fy = sel_first(r[1], ts, toy);
+      const int cx = sel_count(r[0], r[2], ts, tox);
+      const int64_t item = (int64_t)f.item_base[b * nv + v] + (int64_t)((ty - fy) / ts) * cx + (tx - fx) / ts;
+      if (item >= (int64_t)f.max_items) continue;
+      M = fmaxf(M, subf[item * 64 + lane]);
+    }
+    if (M != -INFINITY) {
+      const int K = f.fin->K;
+      const float4* tab = reinterpret_cast<const float4*>(f.fin->table);
+      float x = __builtin_fmaf(M, f.fin->tf_scale, f.fin->tf_bias);
+      x = fminf(fmaxf(x, 0.0f), (float)(K - 1));
+      const int i = min((int)x, K - 2);
+      const float t = x - (float)i;
+      const float4 a = tab[i], b = tab[i + 1];
+      F = make_float4(__builtin_fmaf(t, b.x - a.x, a.x), __builtin_fmaf(t, b.y - a.y, a.y),
+                      __builtin_fmaf(t, b.z - a.z, a.z), __builtin_fmaf(t, b.w - a.w, a.w));
+    }
+    if (px < W && py < H) out[((int64_t)v * H + py) * W + px] = F;
+    return;
+  }
   for (int k = 0; k < n; ++k) {
     const int b = list[k];
     const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;

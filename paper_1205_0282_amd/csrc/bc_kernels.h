@@ -29,13 +29,16 @@ struct BcFramePtrs {
   int32_t* item_base;     // [n_bricks * n_views + 1] first item of entry b * n_views + v
   int32_t* item_perm;     // [n_bricks * n_views + 1] first item of the entry at each queue-order position
   BcCounters* ctr;
-  float4* sub;            // sub-image tiles: [max_items][64]
+  float4* sub;            // sub-image tiles: [max_items][64] (one float per ray, read as
+                          // float[max_items][64], for maximum intensity projection)
   const void* pool;
   uint32_t* occ;          // cell-occupancy bits of every brick
   int32_t ess;            // skip samples in clear cells
   int32_t chunk;          // samples per occupancy-mask chunk of the ray caster (32 or 64)
   int32_t n_queues;       // 8: bricks split over one work queue per XCD; 1: one queue
   int32_t K;              // transfer-function entries
+  int32_t op;             // 0 front-to-back compositing, 1 maximum intensity projection
+  int32_t step_policy;    // 0 the view's fixed step, 1 one sample per voxel slice
   int32_t n_bricks, n_views;
   int32_t gdims[3];
   int64_t max_items;

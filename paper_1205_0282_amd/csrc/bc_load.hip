@@ -1,12 +1,13 @@
 // Load-time kernels: per-brick minimum/maximum of the stored values (the
 // paper's min/max task after the data reaches GPU memory, Section 2.3.1), the
-// FP8 scale/offset, and the encode + layout of ghosted bricks into 4x4x4
+// FP8 scale/offset, the largest decoded value, and the encode + layout of ghosted bricks into 4x4x4
 // micro-blocks (voxels of a micro-block x fastest, micro-blocks row-major
 // inside the brick).
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include "bc_types.h"
 #include "bc_kernels.h"
+#include "bc_e4m3.h"
 
 namespace {
 
@@ -91,25 +92,14 @@ __global__ void finalize_kernel(BcBrick* bricks, const BcCounters* ctr, int firs
   }
   bricks[b].scale = s;
   bricks[b].offs = o;
-}
-
-// round to nearest even on the E4M3 grid, saturating at +-448
-__device__ __forceinline__ uint8_t encode_e4m3(float x) {
-  const uint32_t bits = __float_as_uint(x);
-  const uint32_t sign = (bits >> 31) << 7;
-  if (x != x) return (uint8_t)(sign | 0x7f);
-  float a = fminf(fabsf(x), 448.0f);
-  uint32_t code;
-  if (a < 0.015625f) {                               // below 2^-6: quantum 2^-9
-    code = (uint32_t)rintf(a * 512.0f);              // 0..8 (8 is the smallest normal)
-  } else {
-    int e = (int)((__float_as_uint(a) >> 23) & 255) - 127;   // 2^e <= a < 2^(e+1), e in [-6, 8]
-    float r = rintf(ldexpf(a, 3 - e));               // in [8, 16]
-    uint32_t m = (uint32_t)r;
-    if (m == 16) { m = 8; e += 1; }
-    code = ((uint32_t)(e + 7) << 3) | (m - 8);
-  }
-  return (uint8_t)(sign | code);
+  // the encodes below are monotone (round to nearest, saturating), so the
+  // largest stored element is the encode of the largest source value; its
+  // decode bounds every value the brick can produce (maximum intensity
+  // projection stops a ray there)
+  float dmax = mx;
+  if (storage == 1) dmax = __half2float(__float2half_rn(mx));
+  if (storage == 2) dmax = __builtin_fmaf(bc_e4m3_decode(bc_e4m3_encode((mx - o) * (1.0f / s))), s, o);
+  bricks[b].dmax = dmax;
 }
 
 template <typename T, int FMT>
@@ -140,7 +130,7 @@ __global__ __launch_bounds__(256) void encode_kernel(SrcView s, const BcBrick* b
       static_cast<__half*>(pool)[dst] = __float2half_rn(v);
     } else {
       const float xq = (v - br.offs) * inv;
-      static_cast<uint8_t*>(pool)[dst] = encode_e4m3(xq);
+      static_cast<uint8_t*>(pool)[dst] = bc_e4m3_encode(xq);
     }
   }
 }

@@ -6,6 +6,10 @@
 //            voxels) telling whether any value the cell can interpolate to
 //            maps to a non-zero table entry.  A sample in a clear cell adds
 //            exactly zero to its ray, so it is counted but not evaluated.
+//            For maximum intensity projection a cell is clear when every
+//            value it can take lies in the leading run of colour-map entries
+//            equal to the first one: such a maximum, and every smaller one,
+//            maps to that first entry, so it never changes the pixel.
 //  render    persistent kernel: every wave pulls (brick, view, 8x8 tile) work
 //            items from a device counter and casts the tile's 64 rays
 //            through the brick: ray from the viewer's matrices, clipping to
@@ -29,24 +33,16 @@
 #include "bc_types.h"
 #include "bc_kernels.h"
 #include "bc_df.h"
+#include "bc_e4m3.h"
 
 namespace {
 
 // ------------------------------------------------------------------ storage
-// E4M3 code -> FP32 without branches: the code's exponent and mantissa bits
-// placed at the top of an FP32 mantissa form a number (normal or subnormal) that
-// is 2^-120 times the code's value, so one exact power-of-two product decodes
-// both normal and subnormal codes.
-__device__ __forceinline__ float e4m3_to_f32(uint32_t c) {
-  const float mag = __uint_as_float((c & 0x7fu) << 20) * 1.329227995784916e+36f;   // 2^120
-  return __uint_as_float(__float_as_uint(mag) | ((c & 0x80u) << 24));
-}
-
 template <int FMT>
 __device__ __forceinline__ float decode(uint32_t raw, float s, float o) {
   if (FMT == 0) return __uint_as_float(raw);
   if (FMT == 1) return __half2float(__ushort_as_half((unsigned short)raw));
-  return __builtin_fmaf(e4m3_to_f32(raw), s, o);
+  return __builtin_fmaf(bc_e4m3_decode(raw), s, o);
 }
 
 template <int FMT>
@@ -102,19 +98,28 @@ struct ClassifyArgs {
   const void* pool;
   int32_t n_bricks;
   int32_t max_words;      // largest occupancy word count of a brick
+  int32_t mip;            // classify for maximum intensity projection
 };
 
 template <int FMT>
 __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs a) {
-  __shared__ int32_t nzp[BC_MAX_K + 1];   // nzp[k] = non-zero table entries among the first k
+  __shared__ int32_t nzp[BC_MAX_K + 1];   // nzp[k] = entries that matter among the first k
   __shared__ int32_t part[256];
   const int K = a.fin->K;
   const int tid = threadIdx.x;
-  // block-wide prefix count of entries with non-zero opacity (premultiplied
-  // colour is zero wherever opacity is)
+  // block-wide prefix count of the entries that matter: non-zero opacity when
+  // compositing (premultiplied colour is zero wherever opacity is), different
+  // from the first entry for maximum intensity projection
+  const float4* tab = reinterpret_cast<const float4*>(a.fin->table);
+  const float4 e0 = tab[0];
+  auto matters = [&](int k) -> int {
+    const float4 e = tab[k];
+    if (!a.mip) return e.w != 0.0f;
+    return e.x != e0.x || e.y != e0.y || e.z != e0.z || e.w != e0.w;
+  };
   const int per = (K + 255) / 256;
   int cnt = 0;
-  for (int k = tid * per; k < min(K, (tid + 1) * per); ++k) cnt += a.fin->table[k][3] != 0.0f;
+  for (int k = tid * per; k < min(K, (tid + 1) * per); ++k) cnt += matters(k);
   part[tid] = cnt;
   __syncthreads();
   if (tid == 0) {
@@ -125,7 +130,7 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs a) {
   int run = part[tid];
   for (int k = tid * per; k < min(K, (tid + 1) * per); ++k) {
     nzp[k] = run;
-    run += a.fin->table[k][3] != 0.0f;
+    run += matters(k);
   }
   if (tid == 255) nzp[K] = run;
   __syncthreads();
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs a) {
           float xl = __builtin_fmaf(lo - m, sc, bi), xh = __builtin_fmaf(hi + m, sc, bi);
           xl = fminf(fmaxf(xl, 0.0f), kmax);
           xh = fminf(fmaxf(xh, 0.0f), kmax);
-          const int il = min((int)xl, K - 2), ih = min((int)xh, K - 2) + 1;
+          const int il = a.mip ? 0 : min((int)xl, K - 2), ih = min((int)xh, K - 2) + 1;
           if (nzp[ih + 1] - nzp[il] > 0) bits |= 1u << ((cz << 4) | (cy << 2) | cx);
         }
     a.occ[br.occ_offset + w] = bits;
@@ -229,10 +234,15 @@ struct RaySeg {
   int64_t s[3];          // step vector, 32.32
 };
 
+__device__ __forceinline__ df df_abs(df a) { return df_lt(a, df_from(0.0f)) ? df_neg(a) : a; }
+
 // Ray of pixel (px, py) against brick br: the samples t_j = t_in + (j+1/2) dt
-// of the ray's cube interval that fall in the brick's half-open box.
+// of the ray's cube interval that fall in the brick's half-open box.  The step
+// is the view's, or with the per-voxel policy 1 / max_a |d_a| (consecutive
+// samples one voxel apart along the ray's dominant axis, the discrete ray
+// casting of Section 2.3.2).
 __device__ bool ray_segment(const BcViewParams& vp, const int32_t* gdims, const BcBrick& br, int px, int py,
-                            RaySeg& seg) {
+                            bool per_voxel, RaySeg& seg) {
   const int W = vp.width, H = vp.height;
   const df x = df_mul(df_from((float)(2 * px + 1 - W)), dfv(vp.iw_hi, vp.iw_lo));
   const df y = df_mul(df_from((float)(H - 2 * py - 1)), dfv(vp.ih_hi, vp.ih_lo));
@@ -265,7 +275,11 @@ __device__ bool ray_segment(const BcViewParams& vp, const int32_t* gdims, const 
   const float bhi[3] = {(float)br.hi[0], (float)br.hi[1], (float)br.hi[2]};
   const Slab b = slab_df(o, d, id, blo, bhi);
   if (b.miss || !df_lt(b.t0, b.t1)) return false;
-  const df dt = dfv(vp.dt_hi, vp.dt_lo), idt = dfv(vp.idt_hi, vp.idt_lo);
+  df dt = dfv(vp.dt_hi, vp.dt_lo), idt = dfv(vp.idt_hi, vp.idt_lo);
+  if (per_voxel) {
+    idt = df_max(df_max(df_abs(d[0]), df_abs(d[1])), df_abs(d[2]));
+    dt = df_div(df_from(1.0f), idt);
+  }
   const int n = first_index(t_in, dt, idt, g.t1);
   int j0 = (b.t0.hi == -INFINITY) ? 0 : first_index(t_in, dt, idt, b.t0);
   int j1 = (b.t1.hi == INFINITY) ? n : first_index(t_in, dt, idt, b.t1);
@@ -286,17 +300,22 @@ __device__ __forceinline__ int hi32(int64_t v) { return (int)(v >> 32); }
 __device__ __forceinline__ float frac32(int64_t v) { return (float)(uint32_t)v * 2.3283064365386963e-10f; }
 
 // ------------------------------------------------------------------ render
-template <int FMT, bool TF_LDS, int CHUNK>
+// OP 0: front-to-back compositing into premultiplied RGBA with early
+// termination at opacity tau.  OP 1: maximum intensity projection, the largest
+// sample value per ray (-inf for a ray with no sample in the brick, -FLT_MAX
+// when all its samples fell in clear cells), stopping once it reaches the
+// largest value the brick stores.
+template <int FMT, bool TF_LDS, int CHUNK, int OP>
 __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   // table entry k at 2k, its difference to entry k+1 at 2k+1
-  __shared__ float4 s_tab[TF_LDS ? 2 * BC_TF_LDS : 2];
+  __shared__ float4 s_tab[(TF_LDS && OP == 0) ? 2 * BC_TF_LDS : 2];
   const int lane = threadIdx.x & 63;
   const BcFrameIn* fin = f.fin;
   const int K = fin->K;
   const float tf_scale = fin->tf_scale, tf_bias = fin->tf_bias;
   const float kmax_f = (float)(K - 1);
   const float4* gtab = reinterpret_cast<const float4*>(fin->table);
-  if (TF_LDS) {
+  if (TF_LDS && OP == 0) {
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
       const float4 a = gtab[k], b = gtab[min(k + 1, K - 1)];
       s_tab[2 * k] = a;
@@ -309,6 +328,7 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   const int KB = nb * nv;
   const uint32_t n_items = f.ctr->n_items;
   const bool ess = f.ess != 0;
+  const bool per_voxel = f.step_policy != 0;
   const int ts = fin->tile_stride, tox = fin->tile_ox, toy = fin->tile_oy;
   constexpr uint32_t esz = FMT == 0 ? 4 : (FMT == 1 ? 2 : 1);
   uint64_t nominal = 0, evaluated = 0;
@@ -352,9 +372,12 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
     const BcViewParams& vp = f.views[v];
     const BcBrick& br = f.bricks[b];
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    float mx = -INFINITY;
     RaySeg seg;
-    if (px < vp.width && py < vp.height && ray_segment(vp, f.gdims, br, px, py, seg)) {
+    if (px < vp.width && py < vp.height && ray_segment(vp, f.gdims, br, px, py, per_voxel, seg)) {
       const float tau = vp.tau;
+      const float bound = br.dmax;
+      mx = -FLT_MAX;
       const int cmx = br.hi[0] - br.lo[0], cmy = br.hi[1] - br.lo[1], cmz = br.hi[2] - br.lo[2];
       const int mbx = br.mb[0], mby = br.mb[1];
       const uint32_t WX = (uint32_t)br.occ_w[0], WY = (uint32_t)br.occ_w[1], WX4 = 4u * WX;
@@ -436,6 +459,16 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
             const float c0 = __builtin_fmaf(wy, c10 - c00, c00);
             const float c1 = __builtin_fmaf(wy, c11 - c01, c01);
             const float val = __builtin_fmaf(wz, c1 - c0, c0);
+            ++evaluated;
+            if (OP == 1) {
+              mx = fmaxf(mx, val);
+              if (mx >= bound) {
+                used = k + i + 1;
+                stop = true;
+                break;
+              }
+              continue;
+            }
             float xt = __builtin_fmaf(val, tf_scale, tf_bias);
             xt = fminf(fmaxf(xt, 0.0f), kmax_f);
             const int it = min((int)xt, K - 2);
@@ -455,7 +488,6 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
             acc.y = __builtin_fmaf(om, __builtin_fmaf(ft, dq.y, q0.y), acc.y);
             acc.z = __builtin_fmaf(om, __builtin_fmaf(ft, dq.z, q0.z), acc.z);
             acc.w = __builtin_fmaf(om, __builtin_fmaf(ft, dq.w, q0.w), acc.w);
-            ++evaluated;
             if (acc.w >= tau) {
               used = k + i + 1;
               stop = true;
@@ -469,7 +501,8 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
       }
       nominal += (uint64_t)used;
     }
-    f.sub[(int64_t)item * 64 + lane] = acc;
+    if (OP == 0) f.sub[(int64_t)item * 64 + lane] = acc;
+    else reinterpret_cast<float*>(f.sub)[(int64_t)item * 64 + lane] = mx;
   }
   for (int off = 32; off > 0; off >>= 1) {
     nominal += __shfl_xor(nominal, off);
@@ -484,12 +517,16 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
 template <int FMT>
 hipError_t launch_render_fmt(const BcFramePtrs& f, int n_workgroups, hipStream_t st) {
   const bool lds = f.K <= BC_TF_LDS;
-  if (f.chunk == 32) {
-    if (lds) render_kernel<FMT, true, 32><<<n_workgroups, 256, 0, st>>>(f);
-    else render_kernel<FMT, false, 32><<<n_workgroups, 256, 0, st>>>(f);
+  if (f.op == 1) {
+    // the colour map is applied after the merge: no table in the ray caster
+    if (f.chunk == 32) render_kernel<FMT, false, 32, 1><<<n_workgroups, 256, 0, st>>>(f);
+    else render_kernel<FMT, false, 64, 1><<<n_workgroups, 256, 0, st>>>(f);
+  } else if (f.chunk == 32) {
+    if (lds) render_kernel<FMT, true, 32, 0><<<n_workgroups, 256, 0, st>>>(f);
+    else render_kernel<FMT, false, 32, 0><<<n_workgroups, 256, 0, st>>>(f);
   } else {
-    if (lds) render_kernel<FMT, true, 64><<<n_workgroups, 256, 0, st>>>(f);
-    else render_kernel<FMT, false, 64><<<n_workgroups, 256, 0, st>>>(f);
+    if (lds) render_kernel<FMT, true, 64, 0><<<n_workgroups, 256, 0, st>>>(f);
+    else render_kernel<FMT, false, 64, 0><<<n_workgroups, 256, 0, st>>>(f);
   }
   return hipGetLastError();
 }
@@ -504,6 +541,7 @@ hipError_t bc_launch_classify(const BcFramePtrs& f, int max_words, hipStream_t s
   a.pool = f.pool;
   a.n_bricks = f.n_bricks;
   a.max_words = max_words;
+  a.mip = f.op == 1;
   const int64_t total = (int64_t)f.n_bricks * max_words;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
   if (f.storage == 0) classify_kernel<0><<<grid, 256, 0, st>>>(a);

@@ -30,8 +30,11 @@ struct BcFrameIn {
   int32_t reset_counters;    // the pass starts the frame's sample counters
   int32_t conditional;       // the pass runs only if the validation set the fall-back flag
   float psnr_threshold;      // validation pass: dB below which the frame falls back
-  int32_t pad_[2];
-  float table[BC_MAX_K][4];  // opacity-corrected premultiplied RGBA entries (only K used)
+  int32_t op;                // 0 front-to-back compositing, 1 maximum intensity projection
+  int32_t step_policy;       // 0 the view's fixed step, 1 one sample per voxel slice (per ray)
+  // compositing: opacity-corrected premultiplied RGBA entries; maximum
+  // intensity projection: the straight colour-map entries (only K used)
+  float table[BC_MAX_K][4];
 };
 
 // Derived per-view quantities written by the FP64 setup kernel.  Vectors used
@@ -68,7 +71,9 @@ struct BcBrick {
   int32_t occ_w[3];          // occupancy words per axis (one word = 4 x 4 x 2 cells)
   int32_t pad_;
   float scale, offs;         // decode v = q * scale + offs (FP8); 1, 0 otherwise
-  float vmin, vmax;          // range of the stored (core + ghost) values
+  float vmin, vmax;          // range of the source (core + ghost) values
+  float dmax;                // largest value the stored elements decode to
+  int32_t pad2_;
 };
 
 // Device counters.  The cache lines that the ray-casting waves update with

@@ -15,7 +15,7 @@ def cam_of(v: synth.ViewSpec) -> rc.Camera:
 
 
 def gpu_render(vol, brick, views, tf_rgba, vmin, vmax, storage="f32", src="device", max_tiles=0,
-               keep=False, options=None):
+               keep=False, options=None, op=None):
     import torch
     dims = vol.shape[::-1]
     bc = binding.BrickCaster(0)
@@ -31,6 +31,8 @@ def gpu_render(vol, brick, views, tf_rgba, vmin, vmax, storage="f32", src="devic
         bc.load(np.ascontiguousarray(vol))
     for k, val in (options or {}).items():
         bc.set_option(k, val)
+    if op is not None:
+        bc.set_operator(*op)
     bc.set_transfer_function(tf_rgba, vmin, vmax)
     bc.set_views(views)
     out = bc.render()

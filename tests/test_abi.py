@@ -222,3 +222,16 @@ def test_options_learned_mode_and_upsampler_argument_checks(lib, host_ctx):
     assert lib.bc_autotune(host_ctx, None, None, 2, None) == binding.BC_E_STATE
     ms = (C.c_double * 3)()
     assert lib.bc_get_timing(host_ctx, ms, None) == binding.BC_E_STATE
+
+
+def test_operator_argument_checks(lib, host_ctx):
+    assert lib.bc_set_operator(None, 0, 0) == binding.BC_E_ARG
+    assert lib.bc_set_operator(host_ctx, 2, 0) == binding.BC_E_ARG
+    assert lib.bc_set_operator(host_ctx, -1, 0) == binding.BC_E_ARG
+    assert lib.bc_set_operator(host_ctx, binding.BC_OP_MIP, 2) == binding.BC_E_ARG
+    # compositing corrects its table for one step per frame
+    assert lib.bc_set_operator(host_ctx, binding.BC_OP_COMPOSITE, binding.BC_STEP_PER_VOXEL) == binding.BC_E_UNSUPPORTED
+    assert b"step" in lib.bc_last_error(host_ctx)
+    for op, st in ((binding.BC_OP_MIP, binding.BC_STEP_PER_VOXEL), (binding.BC_OP_MIP, binding.BC_STEP_FIXED),
+                   (binding.BC_OP_COMPOSITE, binding.BC_STEP_FIXED)):
+        assert lib.bc_set_operator(host_ctx, op, st) == binding.BC_OK

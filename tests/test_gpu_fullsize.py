@@ -1,10 +1,12 @@
 """Parity at the benchmark's full size: the 1024^3 FP32 cube (4x4x4 bricks of
-256^3), perspective 1920x1080, step 0.5, termination at 0.99, rendered by the
-same launch configuration bench.py times, against the FP64 oracle at sampled
-pixels (each computed one by one by the oracle)."""
+256^3), perspective 1920x1080, rendered by the same launch configuration
+bench.py times, against the FP64 oracle at sampled pixels (each computed one
+by one by the oracle): compositing with step 0.5 and termination at 0.99, and
+maximum intensity projection with the per-voxel step."""
 import numpy as np
 import pytest
 
+from oracle import mip
 from oracle import raycast as rc
 from paper_1205_0282_amd import binding, synth
 
@@ -13,7 +15,8 @@ from gpu_util import TOL, cam_of
 pytestmark = pytest.mark.gpu
 
 
-def test_cube1024_frame_sampled_pixels():
+@pytest.fixture(scope="module")
+def cube1024():
     import torch
     recipe = synth.RECIPE_1024
     vol = synth.make_cube(recipe, workers=16)
@@ -29,19 +32,49 @@ def test_cube1024_frame_sampled_pixels():
     bc.set_transfer_function(rgba, vmin, vmax)
     stored = rc.store_bricks(vol, rc.brick_grid(dims, (256, 256, 256)))
     tf = rc.TransferFunction(rgba, vmin, vmax)
+    yield dict(bc=bc, stored=stored, tf=tf, dims=dims)
+    bc.close()
+
+
+def _pixels(cam, dims, seed):
+    rng = np.random.default_rng(seed)
+    cand = np.stack([rng.integers(0, 1920, 2000), rng.integers(0, 1080, 2000)], axis=1)
+    o, d = cam.rays(cand[:, 0], cand[:, 1])
+    _, _, hit = rc.global_interval(o, d, dims)
+    return np.concatenate([cand[hit][:96], cand[~hit][:16]])
+
+
+def test_cube1024_frame_sampled_pixels(cube1024):
+    bc, stored, tf, dims = cube1024["bc"], cube1024["stored"], cube1024["tf"], cube1024["dims"]
+    bc.set_operator("composite", "fixed")
     for frame in (0, 23):
         v = synth.orbit_view(dims, frame)
         bc.set_views([v])
         img = bc.render()[0].cpu().numpy().astype(np.float64)
         cam = cam_of(v)
-        rng = np.random.default_rng(100 + frame)
-        cand = np.stack([rng.integers(0, 1920, 2000), rng.integers(0, 1080, 2000)], axis=1)
-        o, d = cam.rays(cand[:, 0], cand[:, 1])
-        _, _, hit = rc.global_interval(o, d, dims)
-        pix = np.concatenate([cand[hit][:96], cand[~hit][:16]])
+        pix = _pixels(cam, dims, 100 + frame)
         res = rc.render_bricked(stored, dims, cam, tf, 0.5, 0.99, pixels=pix)
         err = rc.max_abs_with_branches(img[pix[:, 1], pix[:, 0]], res)
         print(f"frame {frame}: max err {err.max():.3g} over {len(pix)} pixels, {int(res.tie.sum())} near-tie rays")
         assert err[~res.overflow].max() <= TOL
         assert res.image[:, 3].max() > 0.1
-    bc.close()
+
+
+def test_cube1024_mip_per_voxel_sampled_pixels(cube1024):
+    bc, stored, tf, dims = cube1024["bc"], cube1024["stored"], cube1024["tf"], cube1024["dims"]
+    bc.set_operator("mip", "voxel")
+    try:
+        for frame in (5, 40):
+            v = synth.orbit_view(dims, frame)
+            bc.set_views([v])
+            img = bc.render()[0].cpu().numpy().astype(np.float64)
+            cam = cam_of(v)
+            pix = _pixels(cam, dims, 200 + frame)
+            res = mip.render_mip_bricked(stored, dims, cam, tf, "voxel", pixels=pix)
+            err = mip.max_abs_with_branches(img[pix[:, 1], pix[:, 0]], res)
+            print(f"mip frame {frame}: max err {err.max():.3g} over {len(pix)} pixels, "
+                  f"{int(res.tie.sum())} near-tie rays")
+            assert err.max() <= TOL
+            assert np.unique(res.image[res.samples > 0, 0]).size > 20
+    finally:
+        bc.set_operator("composite", "fixed")
