@@ -70,6 +70,9 @@ def load_library(path: str = LIB_PATH):
         return _LIB
     if not os.path.exists(path):
         raise LibraryMissing(f"{path} is not built; run `python -m paper_1205_0282_amd.build`")
+    # PyTorch first: its HIP runtime is then the one the library binds to (a
+    # second runtime loaded ahead of PyTorch's leaves PyTorch without devices)
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P, I, I64, D, F = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_float
     sig = {

@@ -27,6 +27,13 @@
 // chunk it first gathers the 32 occupancy bits (cheap, all lanes in step),
 // then evaluates only the samples whose cell is occupied, lowest first, so a
 // lane's evaluations do not wait for the empty stretches of other lanes.
+//
+// Fewer gathers.  The kernel is bound by the vector-memory path (address and
+// data units, L1), not by arithmetic, so each lane avoids loads it can do
+// without: consecutive samples in the same occupancy word reuse the word (the
+// repeated load gets an out-of-range offset, answered by the range check
+// without a cache access), and consecutive evaluated samples in the same
+// interpolation cell reuse the cell's 8 voxels held in registers.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <float.h>
@@ -65,21 +72,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
   return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
+// voxel at a byte offset inside the brick
 template <int FMT>
-__device__ __forceinline__ float load_voxel(__amdgpu_buffer_rsrc_t r, uint32_t idx, float s, float o) {
-  if (FMT == 0) return decode<0>(__builtin_amdgcn_raw_buffer_load_b32(r, idx * 4u, 0, 0), s, o);
-  if (FMT == 1) return decode<1>(__builtin_amdgcn_raw_buffer_load_b16(r, idx * 2u, 0, 0), s, o);
-  return decode<2>(__builtin_amdgcn_raw_buffer_load_b8(r, idx, 0, 0), s, o);
+__device__ __forceinline__ float load_voxel(__amdgpu_buffer_rsrc_t r, uint32_t ofs, float s, float o) {
+  if (FMT == 0) return decode<0>(__builtin_amdgcn_raw_buffer_load_b32(r, ofs, 0, 0), s, o);
+  if (FMT == 1) return decode<1>(__builtin_amdgcn_raw_buffer_load_b16(r, ofs, 0, 0), s, o);
+  return decode<2>(__builtin_amdgcn_raw_buffer_load_b8(r, ofs, 0, 0), s, o);
 }
-
-// element index, inside the brick, of ghosted local voxel (x, y, z): 4x4x4
-// micro-blocks stored row-major, voxels of a micro-block x fastest
-__device__ __forceinline__ uint32_t vox_index(int x, int y, int z, int mbx, int mby) {
-  const uint32_t blk = (uint32_t)(x >> 2) + __umul24((uint32_t)mbx, (uint32_t)(y >> 2) + __umul24((uint32_t)mby, (uint32_t)(z >> 2)));
-  return (blk << 6) | ((uint32_t)(z & 3) << 4) | ((uint32_t)(y & 3) << 2) | (uint32_t)(x & 3);
-}
-
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // a * b + c on the low 24 bits of a and b (one full-rate instruction; the
 // compiler cannot prove the operands fit 24 bits and would otherwise emit a
@@ -89,6 +88,23 @@ __device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) 
   asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
   return d;
 }
+
+// element index, inside the brick, of ghosted local voxel (x, y, z) >= 0: 4x4x4
+// micro-blocks stored row-major, voxels of a micro-block x fastest
+__device__ __forceinline__ uint32_t vox_index(int x, int y, int z, int mbx, int mby) {
+  const uint32_t blk = mad_u24(mad_u24((uint32_t)z >> 2, (uint32_t)mby, (uint32_t)y >> 2), (uint32_t)mbx,
+                               (uint32_t)x >> 2);
+  return (blk << 6) | ((uint32_t)(z & 3) << 4) | ((uint32_t)(y & 3) << 2) | (uint32_t)(x & 3);
+}
+
+// floor(x) as an integer in one instruction
+__device__ __forceinline__ int floor_i32(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // ------------------------------------------------------------------ classify
 struct ClassifyArgs {
@@ -386,12 +402,20 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
       const uint32_t n_vox = (uint32_t)br.gdim[0] * (uint32_t)br.gdim[1] * (uint32_t)br.gdim[2];
       const __amdgpu_buffer_rsrc_t pool = make_rsrc(static_cast<const char*>(f.pool) + br.offset * esz, n_vox * esz);
       const float s_q = br.scale, o_q = br.offs;
-      const uint32_t dxb = 61u, dyb = (uint32_t)mbx * 64u - 12u, dzb = (uint32_t)mbx * (uint32_t)mby * 64u - 48u;
+      // byte steps to the +x/+y/+z neighbour: inside a micro-block, or across
+      // into the next one (from the last voxel of a micro-block row)
+      constexpr uint32_t sh = FMT == 0 ? 2 : (FMT == 1 ? 1 : 0);
+      const uint32_t dxb = 61u << sh, dyb = ((uint32_t)mbx * 64u - 12u) << sh,
+                     dzb = ((uint32_t)mbx * (uint32_t)mby * 64u - 48u) << sh;
       int64_t uc0 = seg.u[0], uc1 = seg.u[1], uc2 = seg.u[2];
       const int64_t s0 = seg.s[0], s1 = seg.s[1], s2 = seg.s[2];
       const float sfx = (float)s0 * 2.3283064365386963e-10f, sfy = (float)s1 * 2.3283064365386963e-10f,
                   sfz = (float)s2 * 2.3283064365386963e-10f;
       int used = seg.n;
+      // the voxels of the cell the lane interpolated last, and its offset
+      // (none yet)
+      uint32_t cell_ofs = 0xffffffffu;
+      float cv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       for (int k = 0; k < seg.n; k += CHUNK) {
         const int cnt = min(CHUNK, seg.n - k);
         uint64_t mask = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
@@ -401,11 +425,12 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
           // read as clear through the buffer range check)
           // all addresses first, then all loads in flight together
           uint64_t m = 0;
+          uint32_t occ_ofs = 0xffffffffu, occ_word = 0u;   // the occupancy word loaded last
 #pragma unroll
-          for (int h = 0; h < CHUNK / 16; ++h) {
-            uint32_t wofs[16], bit[16], word[16];
+          for (int h = 0; h < CHUNK / 8; ++h) {
+            uint32_t wofs[8], bit[8], word[8];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < 8; ++i) {
               const uint32_t ix = (uint32_t)hi32(un0), iy = (uint32_t)hi32(un1), iz = (uint32_t)hi32(un2);
               // word (ix/4, iy/4, iz/2) as a byte offset; bit (ix%4) + 4 (iy%4) + 16 (iz%2), of
               // which the bit-field extract below reads only the low five bits
@@ -414,12 +439,27 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
               bit[i] = (bxy & 15u) | ((iz << 4) & ~15u);
               un0 += s0; un1 += s1; un2 += s2;
             }
+            // a sample in the same word as the one before it reuses that
+            // word: its load gets an offset past the end of the bits, which
+            // the range check answers without a cache access
+            uint32_t fresh = 0;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) word[i] = __builtin_amdgcn_raw_buffer_load_b32(occ, wofs[i], 0, 0);
+            for (int i = 0; i < 8; ++i) {
+              const uint32_t before = i ? wofs[i - 1] : occ_ofs;
+              fresh |= (uint32_t)(wofs[i] != before) << i;
+            }
+            occ_ofs = wofs[7];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+              word[i] = __builtin_amdgcn_raw_buffer_load_b32(occ, ((fresh >> i) & 1u) ? wofs[i] : 0xfffffff0u, 0, 0);
             uint32_t mh = 0;
+            // (a reused sample's load returned zero: keep the word before)
 #pragma unroll
-            for (int i = 0; i < 16; ++i) mh |= __builtin_amdgcn_ubfe(word[i], bit[i], 1u) << i;
-            m |= (uint64_t)mh << (16 * h);
+            for (int i = 0; i < 8; ++i) {
+              occ_word = word[i] | (occ_word & (((fresh >> i) & 1u) - 1u));
+              mh |= __builtin_amdgcn_ubfe(occ_word, bit[i], 1u) << i;
+            }
+            m |= (uint64_t)mh << (8 * h);
           }
           mask &= m;
         } else {
@@ -440,22 +480,31 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
             const float fi = (float)i;
             const float ux = __builtin_fmaf(fi, sfx, fx0), uy = __builtin_fmaf(fi, sfy, fy0),
                         uz = __builtin_fmaf(fi, sfz, fz0);
-            const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
-            const float wx = ux - flx, wy = uy - fly, wz = uz - flz;
-            const int ix = bx + (int)flx, iy = by + (int)fly, iz = bz + (int)flz;
-            const uint32_t a000 = vox_index(ix, iy, iz, mbx, mby);
-            const uint32_t dx = (ix & 3) == 3 ? dxb : 1u;
-            const uint32_t dy = (iy & 3) == 3 ? dyb : 4u;
-            const uint32_t dz = (iz & 3) == 3 ? dzb : 16u;
-            const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
-            const float v000 = load_voxel<FMT>(pool, a000, s_q, o_q), v100 = load_voxel<FMT>(pool, a000 + dx, s_q, o_q);
-            const float v010 = load_voxel<FMT>(pool, a010, s_q, o_q), v110 = load_voxel<FMT>(pool, a010 + dx, s_q, o_q);
-            const float v001 = load_voxel<FMT>(pool, a001, s_q, o_q), v101 = load_voxel<FMT>(pool, a001 + dx, s_q, o_q);
-            const float v011 = load_voxel<FMT>(pool, a011, s_q, o_q), v111 = load_voxel<FMT>(pool, a011 + dx, s_q, o_q);
-            const float c00 = __builtin_fmaf(wx, v100 - v000, v000);
-            const float c10 = __builtin_fmaf(wx, v110 - v010, v010);
-            const float c01 = __builtin_fmaf(wx, v101 - v001, v001);
-            const float c11 = __builtin_fmaf(wx, v111 - v011, v011);
+            const float wx = __builtin_amdgcn_fractf(ux), wy = __builtin_amdgcn_fractf(uy),
+                        wz = __builtin_amdgcn_fractf(uz);
+            const int ix = bx + floor_i32(ux), iy = by + floor_i32(uy), iz = bz + floor_i32(uz);
+            const uint32_t a000 = vox_index(ix, iy, iz, mbx, mby) << sh;
+            // the 8 voxels of the sample's cell, loaded only when the cell
+            // differs from the one the lane interpolated last
+            if (a000 != cell_ofs) {
+              const uint32_t dx = (ix & 3) == 3 ? dxb : (1u << sh);
+              const uint32_t dy = (iy & 3) == 3 ? dyb : (4u << sh);
+              const uint32_t dz = (iz & 3) == 3 ? dzb : (16u << sh);
+              const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
+              cv[0] = load_voxel<FMT>(pool, a000, s_q, o_q);
+              cv[1] = load_voxel<FMT>(pool, a000 + dx, s_q, o_q);
+              cv[2] = load_voxel<FMT>(pool, a010, s_q, o_q);
+              cv[3] = load_voxel<FMT>(pool, a010 + dx, s_q, o_q);
+              cv[4] = load_voxel<FMT>(pool, a001, s_q, o_q);
+              cv[5] = load_voxel<FMT>(pool, a001 + dx, s_q, o_q);
+              cv[6] = load_voxel<FMT>(pool, a011, s_q, o_q);
+              cv[7] = load_voxel<FMT>(pool, a011 + dx, s_q, o_q);
+              cell_ofs = a000;
+            }
+            const float c00 = __builtin_fmaf(wx, cv[1] - cv[0], cv[0]);
+            const float c10 = __builtin_fmaf(wx, cv[3] - cv[2], cv[2]);
+            const float c01 = __builtin_fmaf(wx, cv[5] - cv[4], cv[4]);
+            const float c11 = __builtin_fmaf(wx, cv[7] - cv[6], cv[6]);
             const float c0 = __builtin_fmaf(wy, c10 - c00, c00);
             const float c1 = __builtin_fmaf(wy, c11 - c01, c01);
             const float val = __builtin_fmaf(wz, c1 - c0, c0);
