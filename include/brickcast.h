@@ -269,10 +269,13 @@ int bc_get_bricks(bc_ctx* ctx, int32_t* lo_hi, float* scale_offset, float* min_m
 int bc_get_visibility_order(bc_ctx* ctx, int view, int32_t* order, int cap);
 int bc_get_rects(bc_ctx* ctx, int view, int32_t* rects, int cap);
 
-/* Copy the stored elements of brick `b` (ghosted, padded to a multiple of 4
- * per axis, 4x4x4 micro-blocks in row-major order, voxels inside a
- * micro-block x fastest) to host memory `dst` of `cap` bytes, and report
- * the padded dims.  For tests of the layout and the encoders. */
+/* Copy the stored elements of brick `b` to host memory `dst` of `cap` bytes
+ * and report the padded dims.  Layout: the ghosted brick padded to a multiple
+ * of 4 per axis, as 4x4x4 micro-blocks in row-major order; a micro-block is 16
+ * rows (y, then z) of 5 elements, the row's 4 voxels (x fastest) followed by
+ * the first voxel of the next micro-block along x (the last voxel of the
+ * padded brick where there is none).  80 elements per micro-block, so
+ * mbx*mby*mbz*80 elements in all.  For tests of the layout and the encoders. */
 int bc_read_brick(bc_ctx* ctx, int b, void* dst, size_t cap, int32_t padded_dims[3]);
 
 /* ---------------------------------------------------------------------------

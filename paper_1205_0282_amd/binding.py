@@ -361,24 +361,42 @@ class BrickCaster:
         self._check(self.lib.bc_read_brick(self.h, b, None, 0, dims))
         gx, gy, gz = dims[0], dims[1], dims[2]
         dt = {"f32": np.float32, "f16": np.uint16, "fp8": np.uint8}[self.storage]
-        buf = np.zeros(gx * gy * gz, dtype=dt)
+        buf = np.zeros((gx // 4) * (gy // 4) * (gz // 4) * 80, dtype=dt)
         self._check(self.lib.bc_read_brick(self.h, b, C.c_void_p(buf.ctypes.data), buf.nbytes, dims))
         return buf, (gx, gy, gz)
 
 
 def unswizzle(buf, padded_dims):
-    """Stored brick elements (4x4x4 micro-blocks, x fastest inside) -> array [z][y][x]
-    of the padded ghosted brick.  For layout tests."""
+    """Stored brick elements -> array [z][y][x] of the padded ghosted brick.
+    Layout: 4x4x4 micro-blocks in row-major order, each 16 rows (y, then z) of
+    5 elements, x fastest, the fifth repeating the first voxel of the next
+    micro-block along x.  For layout tests."""
     gx, gy, gz = padded_dims
     mbx, mby, mbz = gx // 4, gy // 4, gz // 4
-    e = np.arange(gx * gy * gz)
-    mbi, inn = e >> 6, e & 63
-    wx = inn & 3
-    wy = (inn >> 2) & 3
-    wz = inn >> 4
+    e = np.arange(mbx * mby * mbz * 80)
+    mbi, inn = e // 80, e % 80
+    row, wx = inn // 5, inn % 5
+    keep = wx < 4
     x = (mbi % mbx) * 4 + wx
-    y = ((mbi // mbx) % mby) * 4 + wy
-    z = (mbi // (mbx * mby)) * 4 + wz
+    y = ((mbi // mbx) % mby) * 4 + (row & 3)
+    z = (mbi // (mbx * mby)) * 4 + (row >> 2)
     out = np.zeros((gz, gy, gx), dtype=buf.dtype)
-    out[z, y, x] = buf
+    out[z[keep], y[keep], x[keep]] = buf[keep]
     return out
+
+
+def row_tails(buf, padded_dims):
+    """The fifth element of every stored row, with the voxel it repeats (the
+    first voxel of the next micro-block along x, or the row's last voxel at
+    the end of the padded brick), both as flat arrays.  For layout tests."""
+    gx, gy, gz = padded_dims
+    full = unswizzle(buf, padded_dims)
+    mbx, mby, mbz = gx // 4, gy // 4, gz // 4
+    e = np.arange(mbx * mby * mbz * 80)
+    mbi, inn = e // 80, e % 80
+    row, wx = inn // 5, inn % 5
+    t = wx == 4
+    x = np.minimum((mbi % mbx) * 4 + 4, gx - 1)
+    y = ((mbi // mbx) % mby) * 4 + (row & 3)
+    z = (mbi // (mbx * mby)) * 4 + (row >> 2)
+    return buf[t], full[z[t], y[t], x[t]]

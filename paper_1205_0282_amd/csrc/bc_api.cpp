@@ -484,7 +484,7 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
         b.offset = off;
         b.scale = 1.0f;
         b.offs = 0.0f;
-        off += (int64_t)b.gdim[0] * b.gdim[1] * b.gdim[2];
+        off += (int64_t)b.mb[0] * b.mb[1] * b.mb[2] * BC_MB_ELEMS;
         // interpolation cells per axis: core + 1 (between ghosted voxels i, i+1)
         b.occ_w[0] = (b.hi[0] - b.lo[0] + 1 + 3) / 4;
         b.occ_w[1] = (b.hi[1] - b.lo[1] + 1 + 3) / 4;
@@ -626,7 +626,7 @@ int bc_load_bricks(bc_ctx* c, const void* src, const int64_t strides[3], int src
     }
     HIPCHECK(c, bc_launch_minmax(s, hb.lo, hb.hi, ctr, b, st));
     HIPCHECK(c, bc_launch_finalize(dbricks, ctr, b, 1, d.storage, st));
-    const int64_t n_elems = (int64_t)hb.gdim[0] * hb.gdim[1] * hb.gdim[2];
+    const int64_t n_elems = (int64_t)hb.mb[0] * hb.mb[1] * hb.mb[2] * BC_MB_ELEMS;
     HIPCHECK(c, bc_launch_encode(s, dbricks, b, n_elems, d.storage, c->dev[0], st));
     if (!src_on_device) HIPCHECK(c, hipStreamSynchronize(st));
   }
@@ -1113,7 +1113,7 @@ int bc_read_brick(bc_ctx* c, int b, void* dst, size_t cap, int32_t dims[3]) {
   if (!c->loaded) return fail(c, BC_E_STATE, "bc_read_brick: bricks not loaded");
   if (b < 0 || b >= c->n_bricks) return fail(c, BC_E_ARG, "bc_read_brick: brick %d out of range", b);
   const BcBrick& br = c->bricks[b];
-  const size_t bytes = (size_t)br.gdim[0] * br.gdim[1] * br.gdim[2] * c->elem_bytes;
+  const size_t bytes = (size_t)br.mb[0] * br.mb[1] * br.mb[2] * BC_MB_ELEMS * c->elem_bytes;
   if (dims)
     for (int a = 0; a < 3; ++a) dims[a] = br.gdim[a];
   if (!dst) return BC_OK;

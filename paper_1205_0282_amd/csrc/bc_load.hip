@@ -1,8 +1,9 @@
 // Load-time kernels: per-brick minimum/maximum of the stored values (the
 // paper's min/max task after the data reaches GPU memory, Section 2.3.1), the
-// FP8 scale/offset, the largest decoded value, and the encode + layout of ghosted bricks into 4x4x4
-// micro-blocks (voxels of a micro-block x fastest, micro-blocks row-major
-// inside the brick).
+// FP8 scale/offset, the largest decoded value, and the encode + layout of
+// ghosted bricks into 4x4x4 micro-blocks (micro-blocks row-major inside the
+// brick; a micro-block is 16 rows of 5 elements, x fastest, the fifth
+// repeating the first voxel of the next micro-block along x).
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include "bc_types.h"
@@ -105,19 +106,20 @@ __global__ void finalize_kernel(BcBrick* bricks, const BcCounters* ctr, int firs
 template <typename T, int FMT>
 __global__ __launch_bounds__(256) void encode_kernel(SrcView s, const BcBrick* bricks, int b, void* pool) {
   const BcBrick br = bricks[b];
-  const int64_t total = (int64_t)br.gdim[0] * br.gdim[1] * br.gdim[2];
+  const int64_t total = (int64_t)br.mb[0] * br.mb[1] * br.mb[2] * BC_MB_ELEMS;
   const int cx = br.hi[0] - br.lo[0], cy = br.hi[1] - br.lo[1], cz = br.hi[2] - br.lo[2];
   const float inv = 1.0f / br.scale;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t mbi = e >> 6;
-    const int in = (int)(e & 63);
+    const int64_t mbi = e / BC_MB_ELEMS;
+    const int in = (int)(e - mbi * BC_MB_ELEMS);
     const int mbx = (int)(mbi % br.mb[0]);
     const int mby = (int)((mbi / br.mb[0]) % br.mb[1]);
     const int mbz = (int)(mbi / ((int64_t)br.mb[0] * br.mb[1]));
-    const int wx = in & 3;
-    const int wy = (in >> 2) & 3;
-    const int wz = in >> 4;
+    const int row = in / BC_ROW;
+    const int wx = in - row * BC_ROW;   // 0..4: the fifth repeats the next micro-block's first voxel
+    const int wy = row & 3;
+    const int wz = row >> 2;
     // local ghosted index (0 <-> voxel lo-1); padding replicates the last ghost
     const int lx = min(mbx * 4 + wx, cx + 1);
     const int ly = min(mby * 4 + wy, cy + 1);

@@ -72,12 +72,24 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
   return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
-// voxel at a byte offset inside the brick
+// a voxel and its +x neighbour (the next element) at a byte offset inside
+// the brick, with one load
 template <int FMT>
-__device__ __forceinline__ float load_voxel(__amdgpu_buffer_rsrc_t r, uint32_t ofs, float s, float o) {
-  if (FMT == 0) return decode<0>(__builtin_amdgcn_raw_buffer_load_b32(r, ofs, 0, 0), s, o);
-  if (FMT == 1) return decode<1>(__builtin_amdgcn_raw_buffer_load_b16(r, ofs, 0, 0), s, o);
-  return decode<2>(__builtin_amdgcn_raw_buffer_load_b8(r, ofs, 0, 0), s, o);
+__device__ __forceinline__ void load_pair(__amdgpu_buffer_rsrc_t r, uint32_t ofs, float s, float o, float& a, float& b) {
+  if (FMT == 0) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 p = __builtin_amdgcn_raw_buffer_load_b64(r, ofs, 0, 0);
+    a = decode<0>(p.x, s, o);
+    b = decode<0>(p.y, s, o);
+  } else if (FMT == 1) {
+    const uint32_t p = __builtin_amdgcn_raw_buffer_load_b32(r, ofs, 0, 0);
+    a = decode<1>(p & 0xffffu, s, o);
+    b = decode<1>(p >> 16, s, o);
+  } else {
+    const uint32_t p = __builtin_amdgcn_raw_buffer_load_b16(r, ofs, 0, 0);
+    a = decode<2>(p & 0xffu, s, o);
+    b = decode<2>((p >> 8) & 0xffu, s, o);
+  }
 }
 
 // a * b + c on the low 24 bits of a and b (one full-rate instruction; the
@@ -89,12 +101,14 @@ __device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) 
   return d;
 }
 
-// element index, inside the brick, of ghosted local voxel (x, y, z) >= 0: 4x4x4
-// micro-blocks stored row-major, voxels of a micro-block x fastest
+// element index, inside the brick, of ghosted local voxel (x, y, z) >= 0:
+// 4x4x4 micro-blocks stored row-major, each as 16 rows (y, then z) of 5
+// elements, x fastest; element index + 1 is always the voxel at x + 1
 __device__ __forceinline__ uint32_t vox_index(int x, int y, int z, int mbx, int mby) {
   const uint32_t blk = mad_u24(mad_u24((uint32_t)z >> 2, (uint32_t)mby, (uint32_t)y >> 2), (uint32_t)mbx,
                                (uint32_t)x >> 2);
-  return (blk << 6) | ((uint32_t)(z & 3) << 4) | ((uint32_t)(y & 3) << 2) | (uint32_t)(x & 3);
+  const uint32_t in_blk = mad_u24((uint32_t)(z & 3), 4u * BC_ROW, mad_u24((uint32_t)(y & 3), BC_ROW, (uint32_t)(x & 3)));
+  return mad_u24(blk, BC_MB_ELEMS, in_blk);
 }
 
 // floor(x) as an integer in one instruction
@@ -399,14 +413,14 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
       const uint32_t WX = (uint32_t)br.occ_w[0], WY = (uint32_t)br.occ_w[1], WX4 = 4u * WX;
       const uint32_t n_occ = WX * WY * (uint32_t)br.occ_w[2];
       const __amdgpu_buffer_rsrc_t occ = make_rsrc(f.occ + br.occ_offset, n_occ * 4u);
-      const uint32_t n_vox = (uint32_t)br.gdim[0] * (uint32_t)br.gdim[1] * (uint32_t)br.gdim[2];
+      const uint32_t n_vox = (uint32_t)br.mb[0] * (uint32_t)br.mb[1] * (uint32_t)br.mb[2] * BC_MB_ELEMS;
       const __amdgpu_buffer_rsrc_t pool = make_rsrc(static_cast<const char*>(f.pool) + br.offset * esz, n_vox * esz);
       const float s_q = br.scale, o_q = br.offs;
-      // byte steps to the +x/+y/+z neighbour: inside a micro-block, or across
-      // into the next one (from the last voxel of a micro-block row)
+      // byte steps to the +y/+z neighbour: inside a micro-block, or across
+      // into the next one (from its last row or slice)
       constexpr uint32_t sh = FMT == 0 ? 2 : (FMT == 1 ? 1 : 0);
-      const uint32_t dxb = 61u << sh, dyb = ((uint32_t)mbx * 64u - 12u) << sh,
-                     dzb = ((uint32_t)mbx * (uint32_t)mby * 64u - 48u) << sh;
+      const uint32_t dyb = ((uint32_t)mbx * BC_MB_ELEMS - 3u * BC_ROW) << sh,
+                     dzb = ((uint32_t)mbx * (uint32_t)mby * BC_MB_ELEMS - 12u * BC_ROW) << sh;
       int64_t uc0 = seg.u[0], uc1 = seg.u[1], uc2 = seg.u[2];
       const int64_t s0 = seg.s[0], s1 = seg.s[1], s2 = seg.s[2];
       const float sfx = (float)s0 * 2.3283064365386963e-10f, sfy = (float)s1 * 2.3283064365386963e-10f,
@@ -487,18 +501,13 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
             // the 8 voxels of the sample's cell, loaded only when the cell
             // differs from the one the lane interpolated last
             if (a000 != cell_ofs) {
-              const uint32_t dx = (ix & 3) == 3 ? dxb : (1u << sh);
-              const uint32_t dy = (iy & 3) == 3 ? dyb : (4u << sh);
-              const uint32_t dz = (iz & 3) == 3 ? dzb : (16u << sh);
+              const uint32_t dy = (iy & 3) == 3 ? dyb : (BC_ROW << sh);
+              const uint32_t dz = (iz & 3) == 3 ? dzb : ((4u * BC_ROW) << sh);
               const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
-              cv[0] = load_voxel<FMT>(pool, a000, s_q, o_q);
-              cv[1] = load_voxel<FMT>(pool, a000 + dx, s_q, o_q);
-              cv[2] = load_voxel<FMT>(pool, a010, s_q, o_q);
-              cv[3] = load_voxel<FMT>(pool, a010 + dx, s_q, o_q);
-              cv[4] = load_voxel<FMT>(pool, a001, s_q, o_q);
-              cv[5] = load_voxel<FMT>(pool, a001 + dx, s_q, o_q);
-              cv[6] = load_voxel<FMT>(pool, a011, s_q, o_q);
-              cv[7] = load_voxel<FMT>(pool, a011 + dx, s_q, o_q);
+              load_pair<FMT>(pool, a000, s_q, o_q, cv[0], cv[1]);
+              load_pair<FMT>(pool, a010, s_q, o_q, cv[2], cv[3]);
+              load_pair<FMT>(pool, a001, s_q, o_q, cv[4], cv[5]);
+              load_pair<FMT>(pool, a011, s_q, o_q, cv[6], cv[7]);
               cell_ofs = a000;
             }
             const float c00 = __builtin_fmaf(wx, cv[1] - cv[0], cv[0]);

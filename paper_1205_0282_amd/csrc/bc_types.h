@@ -7,7 +7,12 @@
 #define BC_MAX_BRICKS 4096
 #define BC_MAX_K 4096
 #define BC_TILE 8          // screen tile edge (pixels): one wave of 64 rays per work item
-#define BC_MB 4            // micro-block edge (voxels): 64 voxels stored contiguously
+#define BC_MB 4            // micro-block edge (voxels)
+// A 4 x 4 x 4 micro-block is stored as 16 rows (y, z) of 5 elements: voxels
+// x = 0..3 of the row and, fifth, the first voxel of the next micro-block along
+// x, so the +x neighbour of every voxel is the next element (one paired load).
+#define BC_ROW 5
+#define BC_MB_ELEMS 80
 #define BC_TF_LDS 1024     // transfer functions up to this many entries are staged in LDS
 
 // A rendering request as the viewer sends it (FP64, OpenGL column-major).
@@ -65,7 +70,7 @@ struct BcViewParams {
 struct BcBrick {
   int32_t lo[3], hi[3];      // core box, global voxel coordinates
   int32_t gdim[3];           // stored dims: core + 2 ghosts, padded to a multiple of 4
-  int32_t mb[3];             // micro-blocks per axis
+  int32_t mb[3];             // micro-blocks per axis (BC_MB_ELEMS elements each)
   int64_t offset;            // first element of the brick in the pool
   int64_t occ_offset;        // first 32-bit word of the brick's cell-occupancy bits
   int32_t occ_w[3];          // occupancy words per axis (one word = 4 x 4 x 2 cells)

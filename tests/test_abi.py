@@ -64,16 +64,17 @@ def test_create_rejects_bad_args(lib):
 def test_plan_sizes(lib, host_ctx):
     rc, sz = _plan(lib, host_ctx, _desc())
     assert rc == 0
-    # 8 bricks of 32^3 -> ghosted 34 -> padded 36 per axis, 4 bytes each
-    assert sz[0] == 8 * 36 ** 3 * 4
+    # 8 bricks of 32^3 -> ghosted 34 -> padded 36 per axis = 9^3 micro-blocks of
+    # 80 elements (16 rows of 5), 4 bytes each
+    assert sz[0] == 8 * 9 ** 3 * 80 * 4
     assert sz[3] >= 34 ** 3 * 4
     rc, sz16 = _plan(lib, host_ctx, _desc(storage=1))
-    assert rc == 0 and sz16[0] == 8 * 36 ** 3 * 2
+    assert rc == 0 and sz16[0] == 8 * 9 ** 3 * 80 * 2
     rc, sz8 = _plan(lib, host_ctx, _desc(storage=2))
-    assert rc == 0 and sz8[0] == 8 * 36 ** 3
-    # uneven edge bricks: 70 = 32 + 32 + 6 -> padded 36, 36, 8
+    assert rc == 0 and sz8[0] == (8 * 9 ** 3 * 80 + 255) // 256 * 256   # rounded up to 256 B
+    # uneven edge bricks: 70 = 32 + 32 + 6 -> padded 36, 36, 8 -> 9, 9, 2 micro-blocks
     rc, szu = _plan(lib, host_ctx, _desc(dims=(70, 64, 64)))
-    assert rc == 0 and szu[0] == (2 * 36 + 8) * 36 * 36 * 2 * 2 * 4
+    assert rc == 0 and szu[0] == (2 * 9 + 2) * 9 * 9 * 2 * 2 * 80 * 4
 
 
 @pytest.mark.parametrize("field,value", [

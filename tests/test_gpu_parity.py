@@ -89,6 +89,8 @@ def test_stored_bricks_bit_exact(storage):
         g = rc.ghosted_region(vol, b)
         buf, pdims = bc.read_brick(b.index)
         arr = binding.unswizzle(buf, pdims)[:g.shape[0], :g.shape[1], :g.shape[2]]
+        tails, repeated = binding.row_tails(buf, pdims)
+        assert np.array_equal(tails, repeated)
         assert list(lohi[b.index]) == list(b.lo) + list(b.hi)
         assert mm[b.index, 0] == g.min() and mm[b.index, 1] == g.max()
         if storage == "f32":
