@@ -52,6 +52,33 @@ from paper_1205_0282_amd import synth  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 ORBIT = 64
 
+# HBM bytes per launch of the ray-casting kernel, measured with rocprofv3
+# counters (FETCH_SIZE x 2 + WRITE_SIZE x 1, KiB, the scales a plain 1 GiB
+# device copy reads back), mean over the render launches of
+# `bench.py --warmup 0 --repeats 0 --cpu-seconds 0 --check-pixels 0 [options]`
+# (the 64-frame orbit, twice).  Valid only for the kernel sources whose SHA-256
+# is recorded; any other source reports null.
+MEASURED_TRAFFIC = {
+    "sources_sha256": "",
+    "bytes": {},   # "workload/storage/operator/step policy" -> bytes per launch
+}
+KERNEL_SOURCES = ("bc_render.hip", "bc_types.h", "bc_kernels.h", "bc_df.h", "bc_e4m3.h")
+
+
+def kernel_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1205_0282_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key: str):
+    if MEASURED_TRAFFIC["sources_sha256"] != kernel_sha256():
+        return None
+    return MEASURED_TRAFFIC["bytes"].get(key)
+
 WORKLOADS = {
     # name: (recipe, brick edge, width, height, views per launch, source dtype)
     "cube1024_persp1920x1080": (synth.RECIPE_1024, 256, 1920, 1080, 1, "f32"),
@@ -421,7 +448,8 @@ def main():
         "samples_per_frame": tot_samples / args.steps,
         "evaluated_per_frame": float(sum(evaluated[i] for i in idx)) / args.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"{args.workload}/{args.storage}/{args.op}/{args.step_policy}"),
                      "kernel": "render_kernel", "algo_bytes_per_launch": tot_bytes / args.steps},
         "paper_statistic": paper_stat,
         "precision_vs_oracle": precision,
