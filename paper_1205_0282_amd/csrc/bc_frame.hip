@@ -196,11 +196,14 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   const int tid = threadIdx.x;
   const int nv = f.n_views;
   const int nb = f.n_bricks;
-  if (tid < nv) view_params(f.fin->views[tid], f.views[tid]);
+  // a conditional pass without the fall-back flag has no work: only its
+  // (empty) work list below is written
+  const bool skip = f.fin->conditional && !f.ctr->fallback;
+  if (tid < nv && !skip) view_params(f.fin->views[tid], f.views[tid]);
   __syncthreads();
   int np2 = 1;
   while (np2 < nb) np2 <<= 1;
-  for (int v = 0; v < nv; ++v) {
+  for (int v = 0; v < (skip ? 0 : nv); ++v) {
     const BcViewParams& vp = f.views[v];
     for (int i = tid; i < np2; i += blockDim.x) {
       if (i < nb) {
@@ -239,7 +242,6 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   // queue order -- bricks grouped by b % Q -- so that queue q (served first by
   // the waves of XCD q) holds whole bricks and the XCDs' L2 caches hold
   // different bricks.
-  const bool skip = f.fin->conditional && !f.ctr->fallback;
   const int ts = f.fin->tile_stride, tox = f.fin->tile_ox, toy = f.fin->tile_oy;
   const int Q = f.n_queues;
   const int K = nb * nv;

@@ -341,6 +341,7 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   __shared__ float4 s_tab[(TF_LDS && OP == 0) ? 2 * BC_TF_LDS : 2];
   const int lane = threadIdx.x & 63;
   const BcFrameIn* fin = f.fin;
+  if (f.ctr->n_items == 0) return;   // e.g. a conditional pass that is not needed
   const int K = fin->K;
   const float tf_scale = fin->tf_scale, tf_bias = fin->tf_bias;
   const float kmax_f = (float)(K - 1);
@@ -361,7 +362,9 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   const bool per_voxel = f.step_policy != 0;
   const int ts = fin->tile_stride, tox = fin->tile_ox, toy = fin->tile_oy;
   constexpr uint32_t esz = FMT == 0 ? 4 : (FMT == 1 ? 2 : 1);
-  uint64_t nominal = 0, evaluated = 0;
+  // per-lane sample counts (a lane takes at most a few thousand samples per
+  // item and a few dozen items per launch, far below 2^32)
+  uint32_t nominal = 0, evaluated = 0;
   // queue of this workgroup's XCD first (workgroups are dispatched to the
   // XCDs round robin), then the others once it is drained
   const BcCounters* cr = f.ctr;   // read-only lines
@@ -557,18 +560,19 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
         if (stop) break;
         uc0 = un0; uc1 = un1; uc2 = un2;
       }
-      nominal += (uint64_t)used;
+      nominal += (uint32_t)used;
     }
     if (OP == 0) f.sub[(int64_t)item * 64 + lane] = acc;
     else reinterpret_cast<float*>(f.sub)[(int64_t)item * 64 + lane] = mx;
   }
+  uint64_t wave_nominal = nominal, wave_evaluated = evaluated;
   for (int off = 32; off > 0; off >>= 1) {
-    nominal += __shfl_xor(nominal, off);
-    evaluated += __shfl_xor(evaluated, off);
+    wave_nominal += __shfl_xor(wave_nominal, off);
+    wave_evaluated += __shfl_xor(wave_evaluated, off);
   }
-  if (lane == 0 && nominal) {
-    atomicAdd(&f.ctr->nominal, (unsigned long long)nominal);
-    atomicAdd(&f.ctr->evaluated, (unsigned long long)evaluated);
+  if (lane == 0 && wave_nominal) {
+    atomicAdd(&f.ctr->nominal, (unsigned long long)wave_nominal);
+    atomicAdd(&f.ctr->evaluated, (unsigned long long)wave_evaluated);
   }
 }
 
