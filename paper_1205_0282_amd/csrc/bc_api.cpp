@@ -24,10 +24,12 @@ thread_local std::string g_create_error;
 struct GraphKey {
   bool learned = false, ess = false, xcd = false;
   int n_views = 0, W = 0, H = 0, K = 0, chunk = 0, wgs = 0, op = 0, step_policy = 0;
+  int64_t split = 0;   // learned frames: sub-image tiles set aside for the concurrent validation pass (0: serial)
   const void* out = nullptr;
   bool operator==(const GraphKey& o) const {
     return learned == o.learned && ess == o.ess && xcd == o.xcd && n_views == o.n_views && W == o.W && H == o.H && K == o.K &&
-           chunk == o.chunk && wgs == o.wgs && op == o.op && step_policy == o.step_policy && out == o.out;
+           chunk == o.chunk && wgs == o.wgs && op == o.op && step_policy == o.step_policy && split == o.split &&
+           out == o.out;
   }
 };
 struct GraphSlot {
@@ -58,6 +60,9 @@ struct bc_ctx {
   size_t bytes[4] = {0, 0, 0, 0};
   size_t off_bricks = 0, off_fin = 0, off_views = 0, off_order = 0, off_rects = 0, off_item_base = 0,
          off_ctr = 0, off_occ = 0, off_item_perm = 0;
+  // a second set of per-pass arrays, for a pass that runs concurrently with
+  // another (the validation pass of a learned frame)
+  size_t off_views_b = 0, off_order_b = 0, off_rects_b = 0, off_item_base_b = 0, off_item_perm_b = 0, off_ctr_b = 0;
   int max_occ_words = 0;
   void* dev[4] = {nullptr, nullptr, nullptr, nullptr};
   // per-frame input ring (pinned host memory, kPasses pass inputs per slot) and events
@@ -87,6 +92,10 @@ struct bc_ctx {
   // captured frames (one per input slot)
   bool use_graph = false;
   hipStream_t capture_stream = nullptr;
+  // learned frames: second stream for the validation pass, and the events
+  // that fork it from and join it back to the frame's stream
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   GraphSlot graphs[2];
   // cell-occupancy bits are valid for this table (opacity-corrected entries)
   bool occ_valid = false;
@@ -176,9 +185,14 @@ int check_view(bc_ctx* c, const bc_view& v, int idx) {
   return BC_OK;
 }
 
-// host bound on the tiles one view needs: the same rectangle as the device
-// setup, widened by one tile per side
-int64_t view_tiles_bound(const bc_ctx* c, const bc_view& v) {
+// host bound on the work items (brick, selected screen tile) one view needs
+// at a frame size, with one tile of every stride x stride block selected:
+// the same rectangles as the device set-up, widened by one tile per side
+int64_t view_tiles_bound(const bc_ctx* c, const bc_view& v, int W, int H, int stride);
+
+int64_t view_tiles_bound(const bc_ctx* c, const bc_view& v) { return view_tiles_bound(c, v, v.width, v.height, 1); }
+
+int64_t view_tiles_bound(const bc_ctx* c, const bc_view& v, int W, int H, int stride) {
   double M[16], P[16], PM[16];
   rowmajor(v.modelview, M);
   rowmajor(v.projection, P);
@@ -191,8 +205,9 @@ int64_t view_tiles_bound(const bc_ctx* c, const bc_view& v) {
   const bool persp = P[14] == -1.0;
   double eye[3];
   for (int a = 0; a < 3; ++a) eye[a] = -((M[a] * M[3] + M[4 + a] * M[7]) + M[8 + a] * M[11]);
-  const int W = v.width, H = v.height;
   const int TX = (W + BC_TILE - 1) / BC_TILE, TY = (H + BC_TILE - 1) / BC_TILE;
+  // selected tiles among n consecutive ones, wherever the selection starts
+  auto sel = [stride](int64_t n) -> int64_t { return (n + stride - 1) / stride; };
   int64_t total = 0;
   for (const BcBrick& b : c->bricks) {
     bool full = false;
@@ -211,14 +226,14 @@ int64_t view_tiles_bound(const bc_ctx* c, const bc_view& v) {
       xmin = std::min(xmin, px); xmax = std::max(xmax, px);
       ymin = std::min(ymin, py); ymax = std::max(ymax, py);
     }
-    if (full) { total += (int64_t)TX * TY; continue; }
+    if (full) { total += sel(TX) * sel(TY); continue; }
     if (xmax < -2.0 || ymax < -2.0 || xmin > W + 1.0 || ymin > H + 1.0) continue;
     const int x0 = (int)std::max(std::floor(xmin) - 1.0, 0.0), y0 = (int)std::max(std::floor(ymin) - 1.0, 0.0);
     const int x1 = (int)std::min(std::ceil(xmax) + 1.0, (double)(W - 1)), y1 = (int)std::min(std::ceil(ymax) + 1.0, (double)(H - 1));
     if (x1 < x0 || y1 < y0) continue;
     const int tx0 = std::max(x0 / BC_TILE - 1, 0), ty0 = std::max(y0 / BC_TILE - 1, 0);
     const int tx1 = std::min(x1 / BC_TILE + 2, TX), ty1 = std::min(y1 / BC_TILE + 2, TY);
-    total += (int64_t)(tx1 - tx0) * (ty1 - ty0);
+    total += sel(tx1 - tx0) * sel(ty1 - ty0);
   }
   return total;
 }
@@ -316,6 +331,21 @@ BcFramePtrs pass_ptrs(bc_ctx* c, BcFramePtrs f, int pass, int width, int height)
   return f;
 }
 
+// the same pass on the second set of per-pass arrays, with the sub-image
+// tiles [first, first + cap) of the shared buffer
+BcFramePtrs second_slot(bc_ctx* c, BcFramePtrs f, int64_t first, int64_t cap) {
+  char* meta = static_cast<char*>(c->dev[1]);
+  f.views = reinterpret_cast<BcViewParams*>(meta + c->off_views_b);
+  f.order = reinterpret_cast<int32_t*>(meta + c->off_order_b);
+  f.rects = reinterpret_cast<int32_t*>(meta + c->off_rects_b);
+  f.item_base = reinterpret_cast<int32_t*>(meta + c->off_item_base_b);
+  f.item_perm = reinterpret_cast<int32_t*>(meta + c->off_item_perm_b);
+  f.ctr = reinterpret_cast<BcCounters*>(meta + c->off_ctr_b);
+  f.sub = static_cast<float4*>(c->dev[2]) + first * BC_TILE * BC_TILE;
+  f.max_items = cap;
+  return f;
+}
+
 struct CnnLayout {
   size_t w, m, v, g;                 // FP32 parameter vectors
   size_t f1, f2, f3, b3, b2;         // packed fragments: forward 1..3, backward-data 3 and 2
@@ -395,6 +425,9 @@ int bc_create(int hip_device, bc_ctx** out) {
     }
     ok = ok && hipEventCreateWithFlags(&c->frame_done, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
       g_create_error = "bc_create: cannot allocate pinned frame buffers / events";
       bc_destroy(c);
@@ -419,6 +452,9 @@ void bc_destroy(bc_ctx* c) {
     for (GraphSlot& g : c->graphs)
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     if (c->load_staging) (void)hipHostFree(c->load_staging);
   }
   delete c;
@@ -515,6 +551,12 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
   c->off_item_base = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
   c->off_item_perm = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
   c->off_ctr = m; m = align256(m + sizeof(BcCounters));
+  c->off_views_b = m; m = align256(m + sizeof(BcViewParams) * BC_MAX_VIEWS);
+  c->off_order_b = m; m = align256(m + sizeof(int32_t) * BC_MAX_VIEWS * c->n_bricks);
+  c->off_rects_b = m; m = align256(m + sizeof(int32_t) * 4 * BC_MAX_VIEWS * c->n_bricks);
+  c->off_item_base_b = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
+  c->off_item_perm_b = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
+  c->off_ctr_b = m; m = align256(m + sizeof(BcCounters));
   c->off_occ = m; m = align256(m + sizeof(uint32_t) * (size_t)occ_words);
   c->bytes[1] = m;
   c->max_occ_words = (int)max_words;
@@ -755,6 +797,18 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
       c->occ_valid = true;
     }
   }
+  // learned frames: sub-image tiles for a concurrent validation pass, if the
+  // coarse pass and the validation pass fit the buffer together (else the
+  // passes run one after the other)
+  int64_t split = 0;
+  if (c->learned) {
+    int64_t coarse_tiles = 0, val_tiles = 0;
+    for (int i = 0; i < n; ++i) {
+      coarse_tiles += view_tiles_bound(c, c->views[i], W / 2, H / 2, 1);
+      val_tiles += view_tiles_bound(c, c->views[i], W, H, c->val_stride);
+    }
+    if (val_tiles > 0 && coarse_tiles + val_tiles <= c->max_tiles) split = val_tiles;
+  }
   hipEvent_t* ev = nullptr;
   if (c->timing && c->timed_frames < kMaxTimedFrames) {
     const size_t need = 4 * (size_t)(c->timed_frames + 1);
@@ -788,17 +842,43 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
       float* coarse_img = reinterpret_cast<float*>(c->cnn_ws + L.coarse);
       float* val_img = reinterpret_cast<float*>(c->cnn_ws + L.val);
       BcFramePtrs fc = pass_ptrs(c, f, 0, W / 2, H / 2);
-      HIPCHECK(c, bc_launch_setup(fc, s));
-      HIPCHECK(c, bc_launch_render(fc, c->render_workgroups, s));
-      HIPCHECK(c, bc_launch_composite(fc, reinterpret_cast<float4*>(coarse_img), s));
-      if (e) HIPCHECK(c, hipEventRecord(e[1], s));
-      int r = cnn_infer(c, L, coarse_img, out, n, H / 2, W / 2, s);
-      if (r) return r;
-      if (e) HIPCHECK(c, hipEventRecord(e[2], s));
       BcFramePtrs fv = pass_ptrs(c, f, 1, W, H);
-      HIPCHECK(c, bc_launch_setup(fv, s));
-      HIPCHECK(c, bc_launch_render(fv, c->render_workgroups, s));
-      HIPCHECK(c, bc_launch_composite(fv, reinterpret_cast<float4*>(val_img), s));
+      if (split > 0) {
+        // the validation pass has few work items, each a long walk through a
+        // brick: it runs on the second stream, on its own arrays, sub-image
+        // tiles and workgroups, while the coarse pass and the network run
+        const int val_wgs = (int)std::min<int64_t>((split + 3) / 4, std::max(c->render_workgroups / 4, 1));
+        const int main_wgs = std::max(c->render_workgroups - val_wgs, 1);
+        const BcFramePtrs fvb = second_slot(c, fv, c->max_tiles - split, split);
+        fc.max_items = c->max_tiles - split;
+        HIPCHECK(c, hipEventRecord(c->fork_ev, s));
+        HIPCHECK(c, hipStreamWaitEvent(c->aux_stream, c->fork_ev, 0));
+        HIPCHECK(c, bc_launch_setup(fvb, c->aux_stream));
+        HIPCHECK(c, bc_launch_render(fvb, val_wgs, c->aux_stream));
+        HIPCHECK(c, bc_launch_composite(fvb, reinterpret_cast<float4*>(val_img), c->aux_stream));
+        HIPCHECK(c, hipEventRecord(c->join_ev, c->aux_stream));
+        HIPCHECK(c, bc_launch_setup(fc, s));
+        HIPCHECK(c, bc_launch_render(fc, main_wgs, s));
+        HIPCHECK(c, bc_launch_composite(fc, reinterpret_cast<float4*>(coarse_img), s));
+        if (e) HIPCHECK(c, hipEventRecord(e[1], s));
+        int r = cnn_infer(c, L, coarse_img, out, n, H / 2, W / 2, s);
+        if (r) return r;
+        if (e) HIPCHECK(c, hipEventRecord(e[2], s));
+        HIPCHECK(c, hipStreamWaitEvent(s, c->join_ev, 0));
+      } else {
+        HIPCHECK(c, bc_launch_setup(fc, s));
+        HIPCHECK(c, bc_launch_render(fc, c->render_workgroups, s));
+        HIPCHECK(c, bc_launch_composite(fc, reinterpret_cast<float4*>(coarse_img), s));
+        if (e) HIPCHECK(c, hipEventRecord(e[1], s));
+        int r = cnn_infer(c, L, coarse_img, out, n, H / 2, W / 2, s);
+        if (r) return r;
+        if (e) HIPCHECK(c, hipEventRecord(e[2], s));
+        HIPCHECK(c, bc_launch_setup(fv, s));
+        HIPCHECK(c, bc_launch_render(fv, c->render_workgroups, s));
+        HIPCHECK(c, bc_launch_composite(fv, reinterpret_cast<float4*>(val_img), s));
+      }
+      // the decision is written to the first set of counters, which the
+      // conditional pass reads
       HIPCHECK(c, bc_launch_psnr(fv, reinterpret_cast<const float4*>(val_img), reinterpret_cast<const float4*>(out), s));
       BcFramePtrs fp = pass_ptrs(c, f, 2, W, H);
       HIPCHECK(c, bc_launch_setup(fp, s));
@@ -826,6 +906,7 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     key.xcd = c->xcd_queues;
     key.op = c->op;
     key.step_policy = c->step_policy;
+    key.split = split;
     key.out = out;
     GraphSlot& g = c->graphs[slot];
     if (!g.exec || !(g.key == key)) {

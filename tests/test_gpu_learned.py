@@ -88,3 +88,35 @@ def test_validation_psnr_matches_host(setup):
     ref = P.render().cpu().numpy().astype(np.float64)
     mse = np.mean((out - ref) ** 2)
     assert abs(st["psnr_db"] - 10 * np.log10(1 / mse)) < 1e-3
+
+
+def test_concurrent_validation_pass_measures_the_same_frame(setup):
+    """With stride 2 the validation pass runs on the second stream beside the
+    coarse pass and the network.  Its PSNR must be the PSNR over one tile of
+    every 2x2 block of tiles of the upsampled frame against the plain frame:
+    it lies between the best and the worst of the four possible selections,
+    and repeated frames give the same images."""
+    import torch
+    L, P = setup["learned"], setup["plain"]
+    L.set_learned(True, coarse_step=2.0, psnr_threshold_db=-1e9, validate_stride=2)
+    L.set_views(setup["views"])
+    P.set_views(setup["views"])
+    ref = P.render().cpu().numpy().astype(np.float64)
+    first = None
+    for _ in range(3):
+        out = L.render().cpu().numpy().astype(np.float64)
+        st = L.stats()
+        if first is None:
+            first = out
+        assert np.array_equal(out, first)
+        err = (out - ref) ** 2
+        psnrs = []
+        for oy in range(2):
+            for ox in range(2):
+                sel = np.zeros(out.shape[1:3], bool)
+                for ty in range(oy, (out.shape[1] + 7) // 8, 2):
+                    for tx in range(ox, (out.shape[2] + 7) // 8, 2):
+                        sel[ty * 8:ty * 8 + 8, tx * 8:tx * 8 + 8] = True
+                psnrs.append(10 * np.log10(1 / err[:, sel].mean()))
+        assert min(psnrs) - 1e-3 <= st["psnr_db"] <= max(psnrs) + 1e-3
+        assert any(abs(st["psnr_db"] - p) < 1e-3 for p in psnrs)
