@@ -89,6 +89,13 @@ WORKLOADS = {
     # 3000 x 3000 x 1500 FP16 cube (27 GB), 12 x 12 x 6 bricks of 256^3 with
     # uneven edge bricks, four orbit views 90 degrees apart per launch
     "cube3000x3000x1500_f16_4views": (synth.RECIPE_BATCH, 256, 1920, 1080, 4, "f16"),
+    # the paper's frame sizes (1024^2 in its node-scaling figure, 2048^2 in
+    # its frame-size figure) and the shapes of its test cubes (Table 1)
+    "cube1024_persp1024x1024": (synth.RECIPE_1024, 256, 1024, 1024, 1, "f32"),
+    "cube1024_persp2048x2048": (synth.RECIPE_1024, 256, 2048, 2048, 1, "f32"),
+    "hipass1721x1721x1025_persp1024x1024": (synth.RECIPE_HIPASS, 256, 1024, 1024, 1, "f32"),
+    "gass2502x2501x1093_persp1024x1024": (synth.RECIPE_GASS, 256, 1024, 1024, 1, "f32"),
+    "nbody2600_f16_persp1024x1024": (synth.RECIPE_NBODY2600, 256, 1024, 1024, 1, "f16"),
 }
 
 
@@ -425,8 +432,11 @@ def main():
     achieved = tot_bytes / render_s / 1e9
     ms_step = elapsed / args.steps * 1e3
     result = {
-        "metric": "Gsamples/s + fps @1920x1080 on 1024^3 cube" if per_launch == 1 else
-                  "Gsamples/s + launches/s @1920x1080, 4 views per launch, 3000x3000x1500 FP16 cube",
+        "metric": (f"Gsamples/s + fps @{W}x{H} on "
+                   + ("1024^3 cube" if recipe.dims == (1024, 1024, 1024) else "x".join(map(str, recipe.dims)) + " cube"))
+                  if per_launch == 1 else
+                  f"Gsamples/s + launches/s @{W}x{H}, {per_launch} views per launch, "
+                  + "x".join(map(str, recipe.dims)) + " FP16 cube",
         "value": tot_samples / elapsed / 1e9,   # learned frames: nominal samples of the plain frame (equivalent)
         "unit": "Gsamples/s",
         "n_gpus": 1,

@@ -56,6 +56,12 @@ RECIPE_1024 = CubeRecipe((1024, 1024, 1024), seed=2, n_sources=500, sigma_lo=10.
 # 3000 x 3000 x 1500 (about 27 GB in FP16), 5000 sources, sigma U[10, 30].
 RECIPE_BATCH = CubeRecipe((3000, 3000, 1500), seed=4, n_sources=5000, sigma_lo=10.0,
                           sigma_hi=30.0)
+# The shapes of the paper's test cubes (Table 1) with the 1024^3 cube's source
+# density (500 per 1024^3) and width law: HIPASS (12 GB in FP32), GASS (25 GB)
+# and the scaled N-body cube (65.4 GB in FP32; stored here from an FP16 source).
+RECIPE_HIPASS = CubeRecipe((1721, 1721, 1025), seed=5, n_sources=1413, sigma_lo=10.0, sigma_hi=30.0)
+RECIPE_GASS = CubeRecipe((2502, 2501, 1093), seed=6, n_sources=3185, sigma_lo=10.0, sigma_hi=30.0)
+RECIPE_NBODY2600 = CubeRecipe((2600, 2600, 2600), seed=7, n_sources=8185, sigma_lo=10.0, sigma_hi=30.0)
 
 
 def draw_sources(recipe: CubeRecipe):

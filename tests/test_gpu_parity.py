@@ -300,3 +300,28 @@ def test_xcd_queues_and_chunks_do_not_change_the_image(small_cube):
     res = rc.render_bricked(stored, vol.shape[::-1], cam_of(views[0]), tf, 0.5, 0.99)
     err, _, _ = compare(ref[64][0].reshape(-1, 4), res)
     assert err <= TOL
+
+
+@pytest.mark.parametrize("kind", ["persp", "ortho"])
+def test_thin_edge_bricks_like_table1_shapes(kind):
+    """The paper's cube shapes split into 256^3 bricks leave thin edge bricks
+    (1025 = 4 x 256 + 1 for the HIPASS cube).  A cube of 300 x 260 x 257 in
+    128^3 bricks has edge bricks 44, 4 and 1 voxels thick: compositing and
+    maximum intensity projection both match the oracle."""
+    from oracle import mip
+    dims = (300, 260, 257)
+    recipe = synth.CubeRecipe(dims, seed=21, n_sources=60, sigma_lo=4.0, sigma_hi=12.0)
+    vol = synth.make_cube(recipe, workers=8)
+    rgba, vmin, vmax = _ramp(vol)
+    v = synth.orbit_view(dims, 27, kind=kind, width=160, height=120, elevation_deg=35.0)
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (128, 128, 128)))
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    img = gpu_render(vol, (128, 128, 128), [v], rgba, vmin, vmax)
+    res = rc.render_bricked(stored, dims, cam_of(v), tf, 0.5, 0.99)
+    err, _, n_ovf = compare(img[0].reshape(-1, 4), res)
+    assert err <= TOL and n_ovf == 0
+    assert res.image[:, 3].max() > 0.3
+    img = gpu_render(vol, (128, 128, 128), [v], rgba, vmin, vmax, op=("mip", "voxel"))
+    res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, "voxel")
+    err = mip.max_abs_with_branches(img[0].reshape(-1, 4), res)
+    assert err.max() <= TOL
