@@ -489,73 +489,78 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
           // fraction that stays below 1 + CHUNK/2 voxels
           const int bx = hi32(uc0), by = hi32(uc1), bz = hi32(uc2);
           const float fx0 = frac32(uc0), fy0 = frac32(uc1), fz0 = frac32(uc2);
-          for (int half = 0; half < CHUNK / 32 && !stop; ++half) {
-          uint32_t m32 = (uint32_t)(mask >> (32 * half));
-          while (m32) {
-            const int i = 32 * half + (int)__builtin_ctz(m32);
-            m32 &= m32 - 1u;
-            const float fi = (float)i;
-            const float ux = __builtin_fmaf(fi, sfx, fx0), uy = __builtin_fmaf(fi, sfy, fy0),
-                        uz = __builtin_fmaf(fi, sfz, fz0);
-            const float wx = __builtin_amdgcn_fractf(ux), wy = __builtin_amdgcn_fractf(uy),
-                        wz = __builtin_amdgcn_fractf(uz);
-            const int ix = bx + floor_i32(ux), iy = by + floor_i32(uy), iz = bz + floor_i32(uz);
-            const uint32_t a000 = vox_index(ix, iy, iz, mbx, mby) << sh;
-            // the 8 voxels of the sample's cell, loaded only when the cell
-            // differs from the one the lane interpolated last
-            if (a000 != cell_ofs) {
-              const uint32_t dy = (iy & 3) == 3 ? dyb : (BC_ROW << sh);
-              const uint32_t dz = (iz & 3) == 3 ? dzb : ((4u * BC_ROW) << sh);
-              const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
-              load_pair<FMT>(pool, a000, s_q, o_q, cv[0], cv[1]);
-              load_pair<FMT>(pool, a010, s_q, o_q, cv[2], cv[3]);
-              load_pair<FMT>(pool, a001, s_q, o_q, cv[4], cv[5]);
-              load_pair<FMT>(pool, a011, s_q, o_q, cv[6], cv[7]);
-              cell_ofs = a000;
-            }
-            const float c00 = __builtin_fmaf(wx, cv[1] - cv[0], cv[0]);
-            const float c10 = __builtin_fmaf(wx, cv[3] - cv[2], cv[2]);
-            const float c01 = __builtin_fmaf(wx, cv[5] - cv[4], cv[4]);
-            const float c11 = __builtin_fmaf(wx, cv[7] - cv[6], cv[6]);
-            const float c0 = __builtin_fmaf(wy, c10 - c00, c00);
-            const float c1 = __builtin_fmaf(wy, c11 - c01, c01);
-            const float val = __builtin_fmaf(wz, c1 - c0, c0);
-            ++evaluated;
-            if (OP == 1) {
-              mx = fmaxf(mx, val);
-              if (mx >= bound) {
-                used = k + i + 1;
-                stop = true;
-                break;
+          // the sample that ended the ray (the loop runs out instead of
+          // breaking, which keeps the loop's registers in place)
+          int last = CHUNK - 1;
+          for (int half = 0; half < CHUNK / 32; ++half) {
+            uint32_t m32 = stop ? 0u : (uint32_t)(mask >> (32 * half));
+            while (m32) {
+              const int i = 32 * half + (int)__builtin_ctz(m32);
+              m32 &= m32 - 1u;
+              const float fi = (float)i;
+              const float ux = __builtin_fmaf(fi, sfx, fx0), uy = __builtin_fmaf(fi, sfy, fy0),
+                          uz = __builtin_fmaf(fi, sfz, fz0);
+              const float wx = __builtin_amdgcn_fractf(ux), wy = __builtin_amdgcn_fractf(uy),
+                          wz = __builtin_amdgcn_fractf(uz);
+              const int ix = bx + floor_i32(ux), iy = by + floor_i32(uy), iz = bz + floor_i32(uz);
+              const uint32_t a000 = vox_index(ix, iy, iz, mbx, mby) << sh;
+              // the 8 voxels of the sample's cell, loaded only when the cell
+              // differs from the one the lane interpolated last
+              if (a000 != cell_ofs) {
+                const uint32_t dy = (iy & 3) == 3 ? dyb : (BC_ROW << sh);
+                const uint32_t dz = (iz & 3) == 3 ? dzb : ((4u * BC_ROW) << sh);
+                const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
+                load_pair<FMT>(pool, a000, s_q, o_q, cv[0], cv[1]);
+                load_pair<FMT>(pool, a010, s_q, o_q, cv[2], cv[3]);
+                load_pair<FMT>(pool, a001, s_q, o_q, cv[4], cv[5]);
+                load_pair<FMT>(pool, a011, s_q, o_q, cv[6], cv[7]);
+                cell_ofs = a000;
               }
-              continue;
-            }
-            float xt = __builtin_fmaf(val, tf_scale, tf_bias);
-            xt = fminf(fmaxf(xt, 0.0f), kmax_f);
-            const int it = min((int)xt, K - 2);
-            const float ft = xt - (float)it;
-            // table entry and its difference to the next entry
-            float4 q0, dq;
-            if (TF_LDS) {
-              q0 = s_tab[2 * it];
-              dq = s_tab[2 * it + 1];
-            } else {
-              q0 = gtab[it];
-              const float4 q1 = gtab[it + 1];
-              dq = make_float4(q1.x - q0.x, q1.y - q0.y, q1.z - q0.z, q1.w - q0.w);
-            }
-            const float om = 1.0f - acc.w;
-            acc.x = __builtin_fmaf(om, __builtin_fmaf(ft, dq.x, q0.x), acc.x);
-            acc.y = __builtin_fmaf(om, __builtin_fmaf(ft, dq.y, q0.y), acc.y);
-            acc.z = __builtin_fmaf(om, __builtin_fmaf(ft, dq.z, q0.z), acc.z);
-            acc.w = __builtin_fmaf(om, __builtin_fmaf(ft, dq.w, q0.w), acc.w);
-            if (acc.w >= tau) {
-              used = k + i + 1;
-              stop = true;
-              break;
+              const float c00 = __builtin_fmaf(wx, cv[1] - cv[0], cv[0]);
+              const float c10 = __builtin_fmaf(wx, cv[3] - cv[2], cv[2]);
+              const float c01 = __builtin_fmaf(wx, cv[5] - cv[4], cv[4]);
+              const float c11 = __builtin_fmaf(wx, cv[7] - cv[6], cv[6]);
+              const float c0 = __builtin_fmaf(wy, c10 - c00, c00);
+              const float c1 = __builtin_fmaf(wy, c11 - c01, c01);
+              const float val = __builtin_fmaf(wz, c1 - c0, c0);
+              if (OP == 1) {
+                mx = fmaxf(mx, val);
+                if (mx >= bound) {
+                  last = i;
+                  stop = true;
+                  m32 = 0u;
+                }
+                continue;
+              }
+              // clamp to [0, K-1] (the median of three, exact)
+              const float xt = __builtin_amdgcn_fmed3f(__builtin_fmaf(val, tf_scale, tf_bias), 0.0f, kmax_f);
+              const int it = min((int)xt, K - 2);
+              const float ft = xt - (float)it;
+              // table entry and its difference to the next entry
+              float4 q0, dq;
+              if (TF_LDS) {
+                q0 = s_tab[2 * it];
+                dq = s_tab[2 * it + 1];
+              } else {
+                q0 = gtab[it];
+                const float4 q1 = gtab[it + 1];
+                dq = make_float4(q1.x - q0.x, q1.y - q0.y, q1.z - q0.z, q1.w - q0.w);
+              }
+              const float om = 1.0f - acc.w;
+              acc.x = __builtin_fmaf(om, __builtin_fmaf(ft, dq.x, q0.x), acc.x);
+              acc.y = __builtin_fmaf(om, __builtin_fmaf(ft, dq.y, q0.y), acc.y);
+              acc.z = __builtin_fmaf(om, __builtin_fmaf(ft, dq.z, q0.z), acc.z);
+              acc.w = __builtin_fmaf(om, __builtin_fmaf(ft, dq.w, q0.w), acc.w);
+              if (acc.w >= tau) {
+                last = i;
+                stop = true;
+                m32 = 0u;
+              }
             }
           }
-          }
+          // the occupied samples up to the last one evaluated
+          evaluated += (uint32_t)__builtin_popcountll(mask & (~0ull >> (63 - last)));
+          if (stop) used = k + last + 1;
         }
         if (stop) break;
         uc0 = un0; uc1 = un1; uc2 = un2;
