@@ -94,7 +94,8 @@ typedef struct {
  * 2 * (bricks along x + along y + along z) + 4).  Every region is 256-byte aligned by the caller.
  * Errors: BC_E_ARG for null pointers, non-positive dims, a share outside the
  * cube, ghost != 1, unknown storage/src_dtype, max_views not in [1, 4],
- * max_w/max_h not in [1, 16384], more than 4096 bricks. */
+ * max_w/max_h not in [1, 16384], more than 4096 bricks, a brick whose stored
+ * form would take 4 GiB or more (FP32 bricks above about 940 voxels per edge). */
 int bc_plan(bc_ctx* ctx, const bc_volume_desc* desc, int max_views, int max_w, int max_h,
             int64_t max_tiles, size_t bytes_out[4]);
 

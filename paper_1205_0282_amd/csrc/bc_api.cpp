@@ -492,6 +492,17 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
     nbt *= nb[a];
   }
   if (nbt > BC_MAX_BRICKS) return fail(c, BC_E_ARG, "bc_plan: %lld bricks exceed the limit of %d", (long long)nbt, BC_MAX_BRICKS);
+  {
+    // offsets and buffer ranges inside a brick are 32-bit: its stored form
+    // (micro-blocks of BC_MB_ELEMS elements over the ghosted box) must stay
+    // below 4 GiB
+    int64_t mbs = 1;
+    for (int a = 0; a < 3; ++a) mbs *= (std::min<int64_t>(d->brick_dims[a], d->share_hi[a] - d->share_lo[a]) + 2 + 3) / 4;
+    const int64_t eb = d->storage == BC_F32 ? 4 : (d->storage == BC_F16 ? 2 : 1);
+    if (mbs * BC_MB_ELEMS * eb >= (int64_t(1) << 32))
+      return fail(c, BC_E_ARG, "bc_plan: a %dx%dx%d brick takes %lld bytes in this storage, 4 GiB or more", d->brick_dims[0],
+                  d->brick_dims[1], d->brick_dims[2], (long long)(mbs * BC_MB_ELEMS * eb));
+  }
   if (c->bound) return fail(c, BC_E_STATE, "bc_plan: memory already bound to this context");
   c->desc = *d;
   c->max_views = max_views;

@@ -92,14 +92,8 @@ __device__ __forceinline__ void load_pair(__amdgpu_buffer_rsrc_t r, uint32_t ofs
   }
 }
 
-// a * b + c on the low 24 bits of a and b (one full-rate instruction; the
-// compiler cannot prove the operands fit 24 bits and would otherwise emit a
-// 64-bit multiply-add)
-__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
-  uint32_t d;
-  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-  return d;
-}
+// a * b + c on the low 24 bits of a and b (one multiply-add instruction)
+__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) { return __umul24(a, b) + c; }
 
 // element index, inside the brick, of ghosted local voxel (x, y, z) >= 0:
 // 4x4x4 micro-blocks stored row-major, each as 16 rows (y, then z) of 5
@@ -110,6 +104,9 @@ __device__ __forceinline__ uint32_t vox_index(int x, int y, int z, int mbx, int 
   const uint32_t in_blk = mad_u24((uint32_t)(z & 3), 4u * BC_ROW, mad_u24((uint32_t)(y & 3), BC_ROW, (uint32_t)(x & 3)));
   return mad_u24(blk, BC_MB_ELEMS, in_blk);
 }
+
+// a * b + c on signed 24-bit a and b (one multiply-add instruction)
+__device__ __forceinline__ int mad_i24(int a, int b, int c) { return __mul24(a, b) + c; }
 
 // floor(x) as an integer in one instruction
 __device__ __forceinline__ int floor_i32(float x) {
@@ -343,7 +340,10 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   const BcFrameIn* fin = f.fin;
   if (f.ctr->n_items == 0) return;   // e.g. a conditional pass that is not needed
   const int K = fin->K;
-  const float tf_scale = fin->tf_scale, tf_bias = fin->tf_bias;
+  const float tf_scale = fin->tf_scale;
+  // held in a vector register: an FMA can read only one scalar operand
+  float tf_bias = fin->tf_bias;
+  asm volatile("" : "+v"(tf_bias));
   const float kmax_f = (float)(K - 1);
   const float4* gtab = reinterpret_cast<const float4*>(fin->table);
   if (TF_LDS && OP == 0) {
@@ -422,10 +422,19 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
       // byte steps to the +y/+z neighbour: inside a micro-block, or across
       // into the next one (from its last row or slice)
       constexpr uint32_t sh = FMT == 0 ? 2 : (FMT == 1 ? 1 : 0);
-      const uint32_t dyb = ((uint32_t)mbx * BC_MB_ELEMS - 3u * BC_ROW) << sh,
-                     dzb = ((uint32_t)mbx * (uint32_t)mby * BC_MB_ELEMS - 12u * BC_ROW) << sh;
+      uint32_t dyb = ((uint32_t)mbx * BC_MB_ELEMS - 3u * BC_ROW) << sh,
+               dzb = ((uint32_t)mbx * (uint32_t)mby * BC_MB_ELEMS - 12u * BC_ROW) << sh;
+      asm volatile("" : "+v"(dyb), "+v"(dzb));   // (selected per lane below)
+      // the element index of vox_index as a sum of per-axis terms: along x
+      // 80 (x>>2) + (x&3) = 20 x - 19 (x&3), along y and z likewise with the
+      // micro-block row and slice strides; in bytes
+      const uint32_t cxb = 20u << sh, cyb = (20u * (uint32_t)mbx) << sh, czb = (20u * (uint32_t)mbx * (uint32_t)mby) << sh;
+      const int rxb = -(int)(19u << sh), ryb = (int)(BC_ROW << sh) - (int)cyb, rzb = (int)((4u * BC_ROW) << sh) - (int)czb;
       int64_t uc0 = seg.u[0], uc1 = seg.u[1], uc2 = seg.u[2];
       const int64_t s0 = seg.s[0], s1 = seg.s[1], s2 = seg.s[2];
+      // y and z of the occupancy pass scaled by 4 and 16, so that bits 2-3 of
+      // the integer part of y' hold y%4 and bit 4 of z' holds z%2
+      const int64_t s1q = s1 * 4, s2q = s2 * 16;
       const float sfx = (float)s0 * 2.3283064365386963e-10f, sfy = (float)s1 * 2.3283064365386963e-10f,
                   sfz = (float)s2 * 2.3283064365386963e-10f;
       int used = seg.n;
@@ -436,8 +445,8 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
       for (int k = 0; k < seg.n; k += CHUNK) {
         const int cnt = min(CHUNK, seg.n - k);
         uint64_t mask = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
-        int64_t un0 = uc0, un1 = uc1, un2 = uc2;
         if (ess) {
+          int64_t un0 = uc0, un1 = uc1 * 4, un2 = uc2 * 16;
           // occupancy bits of the chunk's samples (cells outside the brick
           // read as clear through the buffer range check)
           // all addresses first, then all loads in flight together
@@ -448,39 +457,34 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
             uint32_t wofs[8], bit[8], word[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-              const uint32_t ix = (uint32_t)hi32(un0), iy = (uint32_t)hi32(un1), iz = (uint32_t)hi32(un2);
-              // word (ix/4, iy/4, iz/2) as a byte offset; bit (ix%4) + 4 (iy%4) + 16 (iz%2), of
+              // x, 4 y + (2 bits), 16 z + (4 bits)
+              const uint32_t ix = (uint32_t)hi32(un0), iy4 = (uint32_t)hi32(un1), iz16 = (uint32_t)hi32(un2);
+              // word (x/4, y/4, z/2) as a byte offset; bit (x%4) + 4 (y%4) + 16 (z%2), of
               // which the bit-field extract below reads only the low five bits
-              wofs[i] = mad_u24(mad_u24(iz >> 1, WY, iy >> 2), WX4, ix & ~3u);
-              const uint32_t bxy = (ix & 3u) | ((iy << 2) & ~3u);
-              bit[i] = (bxy & 15u) | ((iz << 4) & ~15u);
-              un0 += s0; un1 += s1; un2 += s2;
+              wofs[i] = mad_u24(mad_u24(iz16 >> 5, WY, iy4 >> 4), WX4, ix & ~3u);
+              bit[i] = (((ix & 3u) | (iy4 & ~3u)) & 15u) | (iz16 & ~15u);
+              un0 += s0; un1 += s1q; un2 += s2q;
             }
             // a sample in the same word as the one before it reuses that
             // word: its load gets an offset past the end of the bits, which
             // the range check answers without a cache access
-            uint32_t fresh = 0;
+            bool fresh[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              const uint32_t before = i ? wofs[i - 1] : occ_ofs;
-              fresh |= (uint32_t)(wofs[i] != before) << i;
-            }
+            for (int i = 0; i < 8; ++i) fresh[i] = wofs[i] != (i ? wofs[i - 1] : occ_ofs);
             occ_ofs = wofs[7];
 #pragma unroll
             for (int i = 0; i < 8; ++i)
-              word[i] = __builtin_amdgcn_raw_buffer_load_b32(occ, ((fresh >> i) & 1u) ? wofs[i] : 0xfffffff0u, 0, 0);
+              word[i] = __builtin_amdgcn_raw_buffer_load_b32(occ, fresh[i] ? wofs[i] : 0xfffffff0u, 0, 0);
             uint32_t mh = 0;
             // (a reused sample's load returned zero: keep the word before)
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-              occ_word = word[i] | (occ_word & (((fresh >> i) & 1u) - 1u));
+              occ_word = word[i] | (fresh[i] ? 0u : occ_word);
               mh |= __builtin_amdgcn_ubfe(occ_word, bit[i], 1u) << i;
             }
             m |= (uint64_t)mh << (8 * h);
           }
           mask &= m;
-        } else {
-          un0 += CHUNK * s0; un1 += CHUNK * s1; un2 += CHUNK * s2;
         }
         bool stop = false;
         if (mask) {
@@ -502,13 +506,18 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
                           uz = __builtin_fmaf(fi, sfz, fz0);
               const float wx = __builtin_amdgcn_fractf(ux), wy = __builtin_amdgcn_fractf(uy),
                           wz = __builtin_amdgcn_fractf(uz);
-              const int ix = bx + floor_i32(ux), iy = by + floor_i32(uy), iz = bz + floor_i32(uz);
-              const uint32_t a000 = vox_index(ix, iy, iz, mbx, mby) << sh;
+              // the sample's cell (inside the brick: 0 <= ix, iy, iz < 2^24)
+              const uint32_t ix = (uint32_t)(bx + floor_i32(ux)), iy = (uint32_t)(by + floor_i32(uy)),
+                             iz = (uint32_t)(bz + floor_i32(uz));
+              const int ry = (int)(iy & 3u), rz = (int)(iz & 3u);
+              const uint32_t a000 = (uint32_t)mad_i24(
+                  rz, rzb, mad_i24(ry, ryb, mad_i24((int)(ix & 3u), rxb,
+                                                    (int)mad_u24(ix, cxb, mad_u24(iy, cyb, __umul24(iz, czb))))));
               // the 8 voxels of the sample's cell, loaded only when the cell
               // differs from the one the lane interpolated last
               if (a000 != cell_ofs) {
-                const uint32_t dy = (iy & 3) == 3 ? dyb : (BC_ROW << sh);
-                const uint32_t dz = (iz & 3) == 3 ? dzb : ((4u * BC_ROW) << sh);
+                const uint32_t dy = ry == 3 ? dyb : (BC_ROW << sh);
+                const uint32_t dz = rz == 3 ? dzb : ((4u * BC_ROW) << sh);
                 const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
                 load_pair<FMT>(pool, a000, s_q, o_q, cv[0], cv[1]);
                 load_pair<FMT>(pool, a010, s_q, o_q, cv[2], cv[3]);
@@ -534,8 +543,9 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
               }
               // clamp to [0, K-1] (the median of three, exact)
               const float xt = __builtin_amdgcn_fmed3f(__builtin_fmaf(val, tf_scale, tf_bias), 0.0f, kmax_f);
-              const int it = min((int)xt, K - 2);
-              const float ft = xt - (float)it;
+              // (the table in LDS has an entry K-1 with a zero difference)
+              const int it = TF_LDS ? (int)xt : min((int)xt, K - 2);
+              const float ft = TF_LDS ? __builtin_amdgcn_fractf(xt) : xt - (float)it;
               // table entry and its difference to the next entry
               float4 q0, dq;
               if (TF_LDS) {
@@ -563,7 +573,7 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
           if (stop) used = k + last + 1;
         }
         if (stop) break;
-        uc0 = un0; uc1 = un1; uc2 = un2;
+        uc0 += CHUNK * s0; uc1 += CHUNK * s1; uc2 += CHUNK * s2;
       }
       nominal += (uint32_t)used;
     }

@@ -103,6 +103,18 @@ def test_plan_rejects_too_many_bricks_and_views(lib, host_ctx):
     assert rc == binding.BC_E_ARG
 
 
+def test_plan_rejects_bricks_past_32bit_offsets(lib, host_ctx):
+    """Offsets and buffer ranges inside a brick are 32-bit: a 1024^3 FP32 brick
+    (257^3 micro-blocks of 80 elements, 5.4 GB) is refused, the same brick in
+    FP16 (2.7 GB) and a 944^3 FP32 brick (4.26 GB) are accepted (sizes rounded up to 256 B)."""
+    rc, _ = _plan(lib, host_ctx, _desc(dims=(1024, 1024, 1024), brick=(1024, 1024, 1024)))
+    assert rc == binding.BC_E_ARG and b"4 GiB" in lib.bc_last_error(host_ctx)
+    rc, sz = _plan(lib, host_ctx, _desc(dims=(1024, 1024, 1024), brick=(1024, 1024, 1024), storage=1))
+    assert rc == 0 and sz[0] == (257 ** 3 * 80 * 2 + 255) // 256 * 256   # rounded up to 256 B
+    rc, sz = _plan(lib, host_ctx, _desc(dims=(944, 944, 944), brick=(944, 944, 944)))
+    assert rc == 0 and sz[0] == (237 ** 3 * 80 * 4 + 255) // 256 * 256
+
+
 def _tf(lib, h, rgba, K=None, vmin=0.0, vmax=1.0, dt_ref=1.0):
     a = np.ascontiguousarray(rgba, np.float32)
     return lib.bc_set_transfer_function(h, a.ctypes.data_as(C.POINTER(C.c_float)),
