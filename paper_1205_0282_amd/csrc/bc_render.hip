@@ -343,7 +343,7 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   const float tf_scale = fin->tf_scale;
   // held in a vector register: an FMA can read only one scalar operand
   float tf_bias = fin->tf_bias;
-  asm volatile("" : "+v"(tf_bias));
+  if (OP == 0) asm volatile("" : "+v"(tf_bias));
   const float kmax_f = (float)(K - 1);
   const float4* gtab = reinterpret_cast<const float4*>(fin->table);
   if (TF_LDS && OP == 0) {
@@ -424,19 +424,19 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
       constexpr uint32_t sh = FMT == 0 ? 2 : (FMT == 1 ? 1 : 0);
       uint32_t dyb = ((uint32_t)mbx * BC_MB_ELEMS - 3u * BC_ROW) << sh,
                dzb = ((uint32_t)mbx * (uint32_t)mby * BC_MB_ELEMS - 12u * BC_ROW) << sh;
-      asm volatile("" : "+v"(dyb), "+v"(dzb));   // (selected per lane below)
+      if (OP == 0) asm volatile("" : "+v"(dyb), "+v"(dzb));   // (selected per lane below)
       // the element index of vox_index as a sum of per-axis terms: along x
       // 80 (x>>2) + (x&3) = 20 x - 19 (x&3), along y and z likewise with the
       // micro-block row and slice strides; in bytes
       const uint32_t cxb = 20u << sh, cyb = (20u * (uint32_t)mbx) << sh, czb = (20u * (uint32_t)mbx * (uint32_t)mby) << sh;
       const int rxb = -(int)(19u << sh), ryb = (int)(BC_ROW << sh) - (int)cyb, rzb = (int)((4u * BC_ROW) << sh) - (int)czb;
       int64_t uc0 = seg.u[0], uc1 = seg.u[1], uc2 = seg.u[2];
-      const int64_t s0 = seg.s[0], s1 = seg.s[1], s2 = seg.s[2];
-      // y and z of the occupancy pass scaled by 4 and 16, so that bits 2-3 of
-      // the integer part of y' hold y%4 and bit 4 of z' holds z%2
-      const int64_t s1q = s1 * 4, s2q = s2 * 16;
-      const float sfx = (float)s0 * 2.3283064365386963e-10f, sfy = (float)s1 * 2.3283064365386963e-10f,
-                  sfz = (float)s2 * 2.3283064365386963e-10f;
+      // the step, with y and z scaled by 4 and 16 (kept only so, to save
+      // registers) so that in the occupancy pass bits 2-3 of the integer part
+      // of y' hold y%4 and bit 4 of z' holds z%2
+      const int64_t s0 = seg.s[0], s1q = seg.s[1] * 4, s2q = seg.s[2] * 16;
+      const float sfx = (float)s0 * 2.3283064365386963e-10f, sfy = (float)seg.s[1] * 2.3283064365386963e-10f,
+                  sfz = (float)seg.s[2] * 2.3283064365386963e-10f;
       int used = seg.n;
       // the voxels of the cell the lane interpolated last, and its offset
       // (none yet)
@@ -573,7 +573,7 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
           if (stop) used = k + last + 1;
         }
         if (stop) break;
-        uc0 += CHUNK * s0; uc1 += CHUNK * s1; uc2 += CHUNK * s2;
+        uc0 += CHUNK * s0; uc1 += (CHUNK * s1q) >> 2; uc2 += (CHUNK * s2q) >> 4;
       }
       nominal += (uint32_t)used;
     }
