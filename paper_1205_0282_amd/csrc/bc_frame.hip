@@ -192,7 +192,7 @@ __device__ void brick_rect(const BcViewParams& vp, const BcBrick& b, int32_t* r)
 __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   __shared__ double skey[BC_MAX_BRICKS];
   __shared__ int32_t sidx[BC_MAX_BRICKS];
-  __shared__ int32_t spart[1024];
+  __shared__ int32_t spart[1024 + 1];
   const int tid = threadIdx.x;
   const int nv = f.n_views;
   const int nb = f.n_bricks;
@@ -255,15 +255,26 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   };
   int32_t sum = 0;
   for (int k = k0; k < k1; ++k) sum += count_at(k);
-  spart[tid] = sum;
+  // exclusive scan of the threads' sums: within each wave by shuffles, then
+  // over the waves' totals
+  {
+    const int lane = tid & 63, wave = tid >> 6;
+    int32_t x = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) spart[wave] = x;
+    __syncthreads();
+    int32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += spart[w];
+    __syncthreads();
+    spart[tid] = before + x - sum;
+    if (tid == (int)blockDim.x - 1) spart[blockDim.x] = before + x;
+  }
   __syncthreads();
   if (tid == 0) {
-    int32_t run = 0;
-    for (int i = 0; i < (int)blockDim.x; ++i) {
-      const int32_t t = spart[i];
-      spart[i] = run;
-      run += t;
-    }
+    const int32_t run = spart[blockDim.x];
     f.item_perm[K] = run;
     f.item_base[K] = run;
     const uint32_t n_items = (uint32_t)min((int64_t)run, f.max_items);
@@ -347,50 +358,65 @@ __global__ __launch_bounds__(1024) void composite_kernel(BcFramePtrs f, float4* 
   const int px = tx * BC_TILE + (lane & (BC_TILE - 1));
   const int py = ty * BC_TILE + (lane / BC_TILE);
   float4 F = make_float4(0.f, 0.f, 0.f, 0.f);
+  float M = -INFINITY;
   const int n = n_list;
-  if (f.op == 1) {
+  // the list in groups of 64 entries: lane j finds the sub-image tile of
+  // entry j for this wave's screen tile (-1: its rectangle misses the tile),
+  // all lanes' loads in flight together; then the wave folds the tiles in
+  // list order, four sub-image loads in flight
+  for (int base = 0; base < n; base += 64) {
+    const int m = min(64, n - base);
+    int my_item = -1;
+    if (lane < m) {
+      const int b = list[base + lane];
+      const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
+      const int r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+      if (tx >= r0 && tx < r2 && ty >= r1 && ty < r3) {
+        const int fx = sel_first(r0, ts, tox), fy = sel_first(r1, ts, toy);
+        const int cx = sel_count(r0, r2, ts, tox);
+        const int64_t item = (int64_t)f.item_base[b * nv + v] + (int64_t)((ty - fy) / ts) * cx + (tx - fx) / ts;
+        if (item < (int64_t)f.max_items) my_item = (int)item;
+      }
+    }
+    for (int k0 = 0; k0 < m; k0 += 4) {
+      int it[4];
+      float4 S[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) it[u] = k0 + u < m ? __shfl(my_item, k0 + u) : -1;
+      if (f.op == 1) {
+        const float* subf = reinterpret_cast<const float*>(f.sub);
+        float m4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m4[u] = it[u] >= 0 ? subf[(int64_t)it[u] * 64 + lane] : -INFINITY;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) M = fmaxf(M, m4[u]);
+        continue;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        S[u] = it[u] >= 0 ? f.sub[(int64_t)it[u] * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float om = 1.0f - F.w;
+        F.x = __builtin_fmaf(om, S[u].x, F.x);
+        F.y = __builtin_fmaf(om, S[u].y, F.y);
+        F.z = __builtin_fmaf(om, S[u].z, F.z);
+        F.w = __builtin_fmaf(om, S[u].w, F.w);
+      }
+    }
+  }
+  if (f.op == 1 && M != -INFINITY) {
     // maximum intensity projection: the largest brick maximum (any order),
     // then the colour map; no sample anywhere leaves the pixel clear
-    const float* subf = reinterpret_cast<const float*>(f.sub);
-    float M = -INFINITY;
-    for (int k = 0; k < n; ++k) {
-      const int b = list[k];
-      const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
-      if (tx < r[0] || tx >= r[2] || ty < r[1] || ty >= r[3]) continue;
-      const int fx = sel_first(r[0], ts, tox), fy = sel_first(r[1], ts, toy);
-      const int cx = sel_count(r[0], r[2], ts, tox);
-      const int64_t item = (int64_t)f.item_base[b * nv + v] + (int64_t)((ty - fy) / ts) * cx + (tx - fx) / ts;
-      if (item >= (int64_t)f.max_items) continue;
-      M = fmaxf(M, subf[item * 64 + lane]);
-    }
-    if (M != -INFINITY) {
-      const int K = f.fin->K;
-      const float4* tab = reinterpret_cast<const float4*>(f.fin->table);
-      float x = __builtin_fmaf(M, f.fin->tf_scale, f.fin->tf_bias);
-      x = fminf(fmaxf(x, 0.0f), (float)(K - 1));
-      const int i = min((int)x, K - 2);
-      const float t = x - (float)i;
-      const float4 a = tab[i], b = tab[i + 1];
-      F = make_float4(__builtin_fmaf(t, b.x - a.x, a.x), __builtin_fmaf(t, b.y - a.y, a.y),
-                      __builtin_fmaf(t, b.z - a.z, a.z), __builtin_fmaf(t, b.w - a.w, a.w));
-    }
-    if (px < W && py < H) out[((int64_t)v * H + py) * W + px] = F;
-    return;
-  }
-  for (int k = 0; k < n; ++k) {
-    const int b = list[k];
-    const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
-    if (tx < r[0] || tx >= r[2] || ty < r[1] || ty >= r[3]) continue;
-    const int fx = sel_first(r[0], ts, tox), fy = sel_first(r[1], ts, toy);
-    const int cx = sel_count(r[0], r[2], ts, tox);
-    const int64_t item = (int64_t)f.item_base[b * nv + v] + (int64_t)((ty - fy) / ts) * cx + (tx - fx) / ts;
-    if (item >= (int64_t)f.max_items) continue;
-    const float4 S = f.sub[item * 64 + lane];
-    const float om = 1.0f - F.w;
-    F.x = __builtin_fmaf(om, S.x, F.x);
-    F.y = __builtin_fmaf(om, S.y, F.y);
-    F.z = __builtin_fmaf(om, S.z, F.z);
-    F.w = __builtin_fmaf(om, S.w, F.w);
+    const int K = f.fin->K;
+    const float4* tab = reinterpret_cast<const float4*>(f.fin->table);
+    float x = __builtin_fmaf(M, f.fin->tf_scale, f.fin->tf_bias);
+    x = fminf(fmaxf(x, 0.0f), (float)(K - 1));
+    const int i = min((int)x, K - 2);
+    const float t = x - (float)i;
+    const float4 a = tab[i], b = tab[i + 1];
+    F = make_float4(__builtin_fmaf(t, b.x - a.x, a.x), __builtin_fmaf(t, b.y - a.y, a.y),
+                    __builtin_fmaf(t, b.z - a.z, a.z), __builtin_fmaf(t, b.w - a.w, a.w));
   }
   if (px < W && py < H) out[((int64_t)v * H + py) * W + px] = F;
 }
