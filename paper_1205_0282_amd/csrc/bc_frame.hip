@@ -33,19 +33,35 @@ __device__ bool mat4_inv(const double* m, double* inv) {
       a[r][c] = m[r * 4 + c];
       a[r][c + 4] = (r == c) ? 1.0 : 0.0;
     }
+  // (every loop is unrolled and the pivot row is swapped in by selects, so
+  // the matrix stays in registers)
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     int p = c;
+    double best = fabs(a[c][c]);
+#pragma unroll
     for (int r = c + 1; r < 4; ++r)
-      if (fabs(a[r][c]) > fabs(a[p][c])) p = r;
-    if (a[p][c] == 0.0) return false;
-    if (p != c)
-      for (int k = 0; k < 8; ++k) { double t = a[c][k]; a[c][k] = a[p][k]; a[p][k] = t; }
+      if (fabs(a[r][c]) > best) { p = r; best = fabs(a[r][c]); }
+#pragma unroll
+    for (int r = c + 1; r < 4; ++r) {
+      const bool sw = r == p;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double x = a[c][k], y = a[r][k];
+        a[c][k] = sw ? y : x;
+        a[r][k] = sw ? x : y;
+      }
+    }
+    if (a[c][c] == 0.0) return false;
     const double d = a[c][c];
+#pragma unroll
     for (int k = 0; k < 8; ++k) a[c][k] = a[c][k] / d;
+#pragma unroll
     for (int r = 0; r < 4; ++r) {
       if (r == c) continue;
       const double f = a[r][c];
       if (f == 0.0) continue;
+#pragma unroll
       for (int k = 0; k < 8; ++k) a[r][k] = a[r][k] - f * a[c][k];
     }
   }
@@ -61,15 +77,28 @@ __device__ __forceinline__ void split(double v, float& hi, float& lo) {
 
 __device__ void view_params(const BcViewIn& in, BcViewParams& vp) {
 #pragma clang fp contract(off)
-  double M[16], P[16], PM[16], Q[16];
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) {
-      M[r * 4 + c] = in.mv[c * 4 + r];
-      P[r * 4 + c] = in.pr[c * 4 + r];
+  // (ordered so that few matrices are live at once: one thread computes this,
+  // and the 4x4 inverse then fits in registers)
+  double PM[16], Q[16];
+  bool persp;
+  double e[3], dir[3];
+  {
+    double M[16], P[16];
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        M[r * 4 + c] = in.mv[c * 4 + r];
+        P[r * 4 + c] = in.pr[c * 4 + r];
+      }
+    mat4_mul(P, M, PM);
+    persp = (P[12] == 0.0 && P[13] == 0.0 && P[14] == -1.0 && P[15] == 0.0);
+    // eye e_a = -((R0a t0 + R1a t1) + R2a t2), without fused multiply-add
+    for (int a = 0; a < 3; ++a) {
+      e[a] = -((M[0 * 4 + a] * M[3] + M[1 * 4 + a] * M[7]) + M[2 * 4 + a] * M[11]);
+      dir[a] = -M[2 * 4 + a];
     }
-  mat4_mul(P, M, PM);
+  }
+  for (int k = 0; k < 16; ++k) vp.pm[k] = PM[k];
   mat4_inv(PM, Q);
-  const bool persp = (P[12] == 0.0 && P[13] == 0.0 && P[14] == -1.0 && P[15] == 0.0);
   vp.kind = persp ? 0 : 1;
   vp.width = in.width;
   vp.height = in.height;
@@ -80,15 +109,10 @@ __device__ void view_params(const BcViewIn& in, BcViewParams& vp) {
   split(1.0 / (double)in.width, vp.iw_hi, vp.iw_lo);
   split(1.0 / (double)in.height, vp.ih_hi, vp.ih_lo);
   vp.tau = (float)in.tau;
-  // eye e_a = -((R0a t0 + R1a t1) + R2a t2), without fused multiply-add
-  double e[3], dir[3];
   for (int a = 0; a < 3; ++a) {
-    e[a] = -((M[0 * 4 + a] * M[3] + M[1 * 4 + a] * M[7]) + M[2 * 4 + a] * M[11]);
-    dir[a] = -M[2 * 4 + a];
     vp.eye[a] = e[a];
     vp.dir[a] = dir[a];
   }
-  for (int k = 0; k < 16; ++k) vp.pm[k] = PM[k];
   double E[3], A[3], B[3], C[3];
   if (persp) {
     // far point w(x, y) = Q (x, y, 1, 1); direction of dehom(w) - e is w.xyz - e w.w
