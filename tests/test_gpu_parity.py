@@ -332,3 +332,34 @@ def test_thin_edge_bricks_like_table1_shapes(kind, monkeypatch):
     res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, "voxel")
     err = mip.max_abs_with_branches(img[0].reshape(-1, 4), res)
     assert err.max() <= TOL
+
+
+def test_more_than_64_bricks_per_block_of_tiles():
+    """4096 bricks of 4^3 voxels (the brick limit) over a 64^3 cube: each 4x4
+    block of screen tiles meets hundreds of brick rectangles, so the sort-last
+    fold walks its brick list in several slices of 64.  Compositing and
+    maximum intensity projection both match the oracle."""
+    from oracle import mip
+    dims = (64, 64, 64)
+    vol = synth.make_cube(synth.CubeRecipe(dims, seed=31, n_sources=12, sigma_lo=2.0, sigma_hi=5.0), workers=4)
+    rgba, vmin, vmax = _ramp(vol)
+    v = synth.orbit_view(dims, 5, kind="persp", width=64, height=48, elevation_deg=30.0)
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (4, 4, 4)))
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    img, bc = gpu_render(vol, (4, 4, 4), [v], rgba, vmin, vmax, keep=True)
+    rects = bc.rects(0)   # pixel bounds, whole 8x8 tiles
+    bc.close()
+    # bricks whose rectangle meets each 4x4 block of tiles (32x32 pixels)
+    most = 0
+    for y0 in range(0, 48, 32):
+        for x0 in range(0, 64, 32):
+            meet = (rects[:, 0] < x0 + 32) & (rects[:, 2] > x0) & (rects[:, 1] < y0 + 32) & (rects[:, 3] > y0)
+            most = max(most, int(meet.sum()))
+    assert most > 64
+    res = rc.render_bricked(stored, dims, cam_of(v), tf, 0.5, 0.99)
+    err, _, n_ovf = compare(img[0].reshape(-1, 4), res)
+    assert err <= TOL and n_ovf == 0
+    assert res.image[:, 3].max() > 0.3
+    img = gpu_render(vol, (4, 4, 4), [v], rgba, vmin, vmax, op=("mip", "voxel"))
+    res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, "voxel")
+    assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
