@@ -28,12 +28,15 @@
 // then evaluates only the samples whose cell is occupied, lowest first, so a
 // lane's evaluations do not wait for the empty stretches of other lanes.
 //
-// Fewer gathers.  The kernel is bound by the vector-memory path (address and
-// data units, L1), not by arithmetic, so each lane avoids loads it can do
-// without: consecutive samples in the same occupancy word reuse the word (the
-// repeated load gets an out-of-range offset, answered by the range check
-// without a cache access), and consecutive evaluated samples in the same
-// interpolation cell reuse the cell's 8 voxels held in registers.
+// Fewer gathers, fewer instructions.  The kernel is bound by the latency of
+// its gathers (the L1 misses above all) together with instruction issue, not
+// by HBM bandwidth.  So each lane avoids loads it can do without: consecutive
+// samples in the same occupancy word reuse the word (the repeated load gets an
+// out-of-range offset, answered by the range check without a cache access),
+// and consecutive evaluated samples in the same interpolation cell reuse the
+// cell's 8 voxels held in registers.  And the per-sample arithmetic is kept to
+// single instructions where it can be: 24-bit multiply-adds with the strides
+// in scalar registers, a floor-convert, a fract, a median-of-three clamp.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <float.h>
