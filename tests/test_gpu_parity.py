@@ -363,3 +363,34 @@ def test_more_than_64_bricks_per_block_of_tiles():
     img = gpu_render(vol, (4, 4, 4), [v], rgba, vmin, vmax, op=("mip", "voxel"))
     res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, "voxel")
     assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
+
+
+@pytest.mark.parametrize("dims,brick", [((1, 1, 1), (1, 1, 1)), ((2, 1, 3), (1, 1, 2)), ((5, 1, 1), (2, 1, 1)),
+                                        ((3, 4, 1), (3, 4, 1))])
+def test_smallest_cubes_bricks_and_frames(dims, brick):
+    """The smallest geometry the method has: cubes one voxel thick, bricks of a
+    single voxel (ghosts on every side are clamped copies), frames of 1x1,
+    3x2 and 9x7 pixels, and an axis-aligned orthographic view with one pixel
+    per voxel column.  Compositing and maximum intensity projection against
+    the oracle."""
+    from oracle import mip
+    rng = np.random.default_rng(41 + sum(dims))
+    vol = rng.uniform(-1, 1, dims[::-1]).astype(np.float32)
+    rgba = synth.random_tf(rng, 16, alpha_max=0.7)
+    tf = rc.TransferFunction(rgba, -1.0, 1.0)
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, brick))
+    views = [synth.orbit_view(dims, f, kind=k, width=w, height=h, elevation_deg=25.0, step=0.37, ert=0.8)
+             for f, k, w, h in ((3, "persp", 1, 1), (19, "ortho", 3, 2), (35, "persp", 9, 7))]
+    views.append(synth.axis_view(dims, "z", dims[0], dims[1], step=0.5, ert=1.0))
+    lit = 0
+    for v in views:
+        img = gpu_render(vol, brick, [v], rgba, -1.0, 1.0)
+        res = rc.render_bricked(stored, dims, cam_of(v), tf, v.step, v.ert)
+        err, _, n_ovf = compare(img[0].reshape(-1, 4), res)
+        assert err <= TOL and n_ovf == 0, (v.width, v.height, err)
+        lit += int(res.image[:, 3].max() > 0.2)
+    assert lit >= 3
+    v = views[2]
+    img = gpu_render(vol, brick, [v], rgba, -1.0, 1.0, op=("mip", "voxel"))
+    res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, "voxel")
+    assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
