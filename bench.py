@@ -59,7 +59,7 @@ ORBIT = 64
 # (the 64-frame orbit, twice).  Valid only for the kernel sources whose SHA-256
 # is recorded; any other source reports null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "c13b81d8d0ae337260e3ccf1da0c4ad3838c971ae60dc2a65d557ee8acca9565",
+    "sources_sha256": "358ab4f38b6cd07b38e83e4d8d0b9cfcf137133eae7e6fbdee1289b031c687ea",
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
         "cube1024_persp1920x1080/f32/composite/fixed": 2426964182,
         "cube1024_persp1920x1080/f32/mip/voxel": 2512300817,

@@ -89,9 +89,13 @@ __device__ __forceinline__ void load_pair(__amdgpu_buffer_rsrc_t r, uint32_t ofs
     a = decode<1>(p & 0xffffu, s, o);
     b = decode<1>(p >> 16, s, o);
   } else {
+    // the hardware conversion of two E4M3 bytes is exact, as is the decode
+    // above (the pool never holds the NaN codes: the encoder saturates)
+    typedef float f2 __attribute__((ext_vector_type(2)));
     const uint32_t p = __builtin_amdgcn_raw_buffer_load_b16(r, ofs, 0, 0);
-    a = decode<2>(p & 0xffu, s, o);
-    b = decode<2>((p >> 8) & 0xffu, s, o);
+    const f2 v = __builtin_amdgcn_cvt_pk_f32_fp8((int)p, false);
+    a = __builtin_fmaf(v.x, s, o);
+    b = __builtin_fmaf(v.y, s, o);
   }
 }
 
