@@ -59,7 +59,7 @@ ORBIT = 64
 # (the 64-frame orbit, twice).  Valid only for the kernel sources whose SHA-256
 # is recorded; any other source reports null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "358ab4f38b6cd07b38e83e4d8d0b9cfcf137133eae7e6fbdee1289b031c687ea",
+    "sources_sha256": "b86a55c8fd4ee992791963e43b10a8216851df2b097ba1ffe219a8ce2fe37296",
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
         "cube1024_persp1920x1080/f32/composite/fixed": 2426964182,
         "cube1024_persp1920x1080/f32/mip/voxel": 2512300817,

@@ -328,6 +328,7 @@ BcFramePtrs pass_ptrs(bc_ctx* c, BcFramePtrs f, int pass, int width, int height)
   f.fin = reinterpret_cast<const BcFrameIn*>(static_cast<char*>(c->dev[1]) + c->off_fin + sizeof(BcFrameIn) * pass);
   f.width = width;
   f.height = height;
+  f.urgent = 0;
   return f;
 }
 
@@ -860,7 +861,9 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
         // tiles and workgroups, while the coarse pass and the network run
         const int val_wgs = (int)std::min<int64_t>((split + 3) / 4, std::max(c->render_workgroups / 4, 1));
         const int main_wgs = std::max(c->render_workgroups - val_wgs, 1);
-        const BcFramePtrs fvb = second_slot(c, fv, c->max_tiles - split, split);
+        BcFramePtrs fvb = second_slot(c, fv, c->max_tiles - split, split);
+        // few long items that gate the frame, beside the whole coarse pass
+        fvb.urgent = 1;
         fc.max_items = c->max_tiles - split;
         HIPCHECK(c, hipEventRecord(c->fork_ev, s));
         HIPCHECK(c, hipStreamWaitEvent(c->aux_stream, c->fork_ev, 0));

@@ -113,11 +113,19 @@ constexpr int PSTRIDE = 40;   // BF16 elements per pixel of a 32-channel LDS til
 
 // ------------------------------------------------------------------ inference
 // One 16x16 tile of coarse pixels per workgroup: input tile with a 3-pixel
-// halo, both hidden activations in LDS, output 32x32 fine pixels.
+// halo, both hidden activations in LDS, output 32x32 fine pixels.  The last
+// layer's results go to an LDS output tile (in the first activation's space,
+// free by then) and leave as whole fine pixels, with the bilinear skip read
+// from an FP32 copy of the input (in the BF16 input tile's space, free after
+// the first layer).
+constexpr int XF = 18;   // FP32 input pixels per side for the bilinear skip of a tile
 __global__ __launch_bounds__(256) void infer_kernel(CnnInferArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t xs[22 * 22 * 4];
+  __shared__ __attribute__((aligned(16))) float xbuf[XF * XF * 4];   // BF16 22x22x4 input, then FP32 18x18x4
   __shared__ __attribute__((aligned(16))) uint16_t a1[20 * 20 * PSTRIDE];
   __shared__ __attribute__((aligned(16))) uint16_t a2[18 * 18 * PSTRIDE];
+  static_assert(sizeof(uint16_t) * 22 * 22 * 4 <= sizeof(float) * XF * XF * 4, "input tile fits");
+  static_assert(sizeof(uint16_t) * 20 * 20 * PSTRIDE >= sizeof(float) * 32 * 32 * 4, "output tile fits");
+  uint16_t* xs = reinterpret_cast<uint16_t*>(xbuf);
   const int H = a.h, W = a.w;
   const int n = blockIdx.z;
   const int oy = blockIdx.y * 16, ox = blockIdx.x * 16;
@@ -141,6 +149,12 @@ __global__ __launch_bounds__(256) void infer_kernel(CnnInferArgs a) {
     a1[p * PSTRIDE + c] = in ? bf16_bits(fmaxf(z + b1[c], 0.0f)) : (uint16_t)0;
   });
   __syncthreads();
+  // FP32 input rows oy-1 .. oy+16 and columns ox-1 .. ox+16, clamped to the
+  // image as the bilinear skip clamps them
+  for (int i = threadIdx.x; i < XF * XF; i += blockDim.x) {
+    const int gy = min(max(oy - 1 + i / XF, 0), H - 1), gx = min(max(ox - 1 + i % XF, 0), W - 1);
+    reinterpret_cast<float4*>(xbuf)[i] = reinterpret_cast<const float4*>(x)[(int64_t)gy * W + gx];
+  }
   const float* b2 = bias + CNN_OFF_B2;
   conv_tile<32, 9, 2>(a1, 20, PSTRIDE, 324, 18, a.wf2, [&](int p, int c, float z) {
     const int gy = oy - 1 + p / 18, gx = ox - 1 + p % 18;
@@ -148,14 +162,41 @@ __global__ __launch_bounds__(256) void infer_kernel(CnnInferArgs a) {
     a2[p * PSTRIDE + c] = in ? bf16_bits(fmaxf(z + b2[c], 0.0f)) : (uint16_t)0;
   });
   __syncthreads();
+  float* ot = reinterpret_cast<float*>(a1);   // [32][32] fine pixels x 4 channels
   const float* b3 = bias + CNN_OFF_B3;
   conv_tile<32, 9, 1>(a2, 18, PSTRIDE, 256, 16, a.wf3, [&](int p, int ch, float z) {
-    const int gy = oy + p / 16, gx = ox + p % 16;
-    if (gy >= H || gx >= W) return;
     const int c = ch >> 2, dy = (ch >> 1) & 1, dx = ch & 1;
-    const int Y = 2 * gy + dy, X = 2 * gx + dx;
-    out[((int64_t)Y * 2 * W + X) * 4 + c] = (z + b3[ch]) + bilinear2(x, H, W, Y, X, c);
+    ot[((2 * (p / 16) + dy) * 32 + 2 * (p % 16) + dx) * 4 + c] = z + b3[ch];
   });
+  __syncthreads();
+  // out = shuffled network output + bilinear x2 of x (half-pixel centres,
+  // clamp to edge), whole fine pixels per thread
+  for (int i = threadIdx.x; i < 32 * 32; i += blockDim.x) {
+    const int fy = i / 32, fx = i % 32;
+    const int Y = 2 * oy + fy, X = 2 * ox + fx;
+    if (Y >= 2 * H || X >= 2 * W) continue;
+    const float cy = ((float)Y + 0.5f) * 0.5f - 0.5f, cx = ((float)X + 0.5f) * 0.5f - 0.5f;
+    const float fy0 = floorf(cy), fx0 = floorf(cx);
+    const float ty = cy - fy0, tx = cx - fx0;
+    const int y0 = min(max((int)fy0, 0), H - 1) - (oy - 1), y1 = min(max((int)fy0 + 1, 0), H - 1) - (oy - 1);
+    const int x0 = min(max((int)fx0, 0), W - 1) - (ox - 1), x1 = min(max((int)fx0 + 1, 0), W - 1) - (ox - 1);
+    const float4 v00 = reinterpret_cast<const float4*>(xbuf)[y0 * XF + x0];
+    const float4 v01 = reinterpret_cast<const float4*>(xbuf)[y0 * XF + x1];
+    const float4 v10 = reinterpret_cast<const float4*>(xbuf)[y1 * XF + x0];
+    const float4 v11 = reinterpret_cast<const float4*>(xbuf)[y1 * XF + x1];
+    const float4 z = reinterpret_cast<const float4*>(ot)[i];
+    auto bl = [&](float a00, float a01, float a10, float a11) {
+      const float top = a00 * (1.0f - tx) + a01 * tx;
+      const float bot = a10 * (1.0f - tx) + a11 * tx;
+      return top * (1.0f - ty) + bot * ty;
+    };
+    float4 o;
+    o.x = z.x + bl(v00.x, v01.x, v10.x, v11.x);
+    o.y = z.y + bl(v00.y, v01.y, v10.y, v11.y);
+    o.z = z.z + bl(v00.z, v01.z, v10.z, v11.z);
+    o.w = z.w + bl(v00.w, v01.w, v10.w, v11.w);
+    reinterpret_cast<float4*>(out)[(int64_t)Y * 2 * W + X] = o;
+  }
 }
 
 // ------------------------------------------------------------------ training forward / backward-data

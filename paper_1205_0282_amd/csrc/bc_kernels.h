@@ -44,6 +44,8 @@ struct BcFramePtrs {
   int64_t max_items;
   int32_t storage;
   int32_t width, height;  // frame size (all views share it)
+  int32_t urgent;         // 1: the ray caster's waves raise their issue priority (a pass that
+                          // runs beside another and holds up the frame)
 };
 
 hipError_t bc_launch_setup(const BcFramePtrs& f, hipStream_t st);

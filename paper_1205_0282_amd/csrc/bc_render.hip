@@ -339,13 +339,17 @@ __device__ __forceinline__ float frac32(int64_t v) { return (float)(uint32_t)v *
 // sample value per ray (-inf for a ray with no sample in the brick, -FLT_MAX
 // when all its samples fell in clear cells), stopping once it reaches the
 // largest value the brick stores.
-template <int FMT, bool TF_LDS, int CHUNK, int OP>
+// URGENT: the waves raise their issue priority (a pass that runs beside
+// another and holds up the frame); a template parameter so that the other
+// instantiations are compiled as if it did not exist.
+template <int FMT, bool TF_LDS, int CHUNK, int OP, bool URGENT>
 __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   // table entry k at 2k, its difference to entry k+1 at 2k+1
   __shared__ float4 s_tab[(TF_LDS && OP == 0) ? 2 * BC_TF_LDS : 2];
   const int lane = threadIdx.x & 63;
   const BcFrameIn* fin = f.fin;
   if (f.ctr->n_items == 0) return;   // e.g. a conditional pass that is not needed
+  if (URGENT) __builtin_amdgcn_s_setprio(2);
   const int K = fin->K;
   const float tf_scale = fin->tf_scale;
   // held in a vector register: an FMA can read only one scalar operand
@@ -603,14 +607,16 @@ hipError_t launch_render_fmt(const BcFramePtrs& f, int n_workgroups, hipStream_t
   const bool lds = f.K <= BC_TF_LDS;
   if (f.op == 1) {
     // the colour map is applied after the merge: no table in the ray caster
-    if (f.chunk == 32) render_kernel<FMT, false, 32, 1><<<n_workgroups, 256, 0, st>>>(f);
-    else render_kernel<FMT, false, 64, 1><<<n_workgroups, 256, 0, st>>>(f);
+    if (f.chunk == 32) render_kernel<FMT, false, 32, 1, false><<<n_workgroups, 256, 0, st>>>(f);
+    else render_kernel<FMT, false, 64, 1, false><<<n_workgroups, 256, 0, st>>>(f);
   } else if (f.chunk == 32) {
-    if (lds) render_kernel<FMT, true, 32, 0><<<n_workgroups, 256, 0, st>>>(f);
-    else render_kernel<FMT, false, 32, 0><<<n_workgroups, 256, 0, st>>>(f);
+    if (lds && f.urgent) render_kernel<FMT, true, 32, 0, true><<<n_workgroups, 256, 0, st>>>(f);
+    else if (lds) render_kernel<FMT, true, 32, 0, false><<<n_workgroups, 256, 0, st>>>(f);
+    else render_kernel<FMT, false, 32, 0, false><<<n_workgroups, 256, 0, st>>>(f);
   } else {
-    if (lds) render_kernel<FMT, true, 64, 0><<<n_workgroups, 256, 0, st>>>(f);
-    else render_kernel<FMT, false, 64, 0><<<n_workgroups, 256, 0, st>>>(f);
+    if (lds && f.urgent) render_kernel<FMT, true, 64, 0, true><<<n_workgroups, 256, 0, st>>>(f);
+    else if (lds) render_kernel<FMT, true, 64, 0, false><<<n_workgroups, 256, 0, st>>>(f);
+    else render_kernel<FMT, false, 64, 0, false><<<n_workgroups, 256, 0, st>>>(f);
   }
   return hipGetLastError();
 }
