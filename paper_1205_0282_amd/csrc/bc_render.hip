@@ -499,6 +499,10 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
         }
         bool stop = false;
         if (mask) {
+          // a wave evaluating samples waits on dependent gathers; letting it
+          // issue ahead of the waves gathering occupancy bits (whose loads are
+          // all in flight together) shortens the frame
+          __builtin_amdgcn_s_setprio(URGENT ? 3 : 1);
           // sample positions inside the chunk in FP32, relative to the
           // chunk's first sample: integer cell of that sample plus a
           // fraction that stays below 1 + CHUNK/2 voxels
@@ -579,6 +583,7 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
               }
             }
           }
+          __builtin_amdgcn_s_setprio(URGENT ? 2 : 0);
           // the occupied samples up to the last one evaluated
           evaluated += (uint32_t)__builtin_popcountll(mask & (~0ull >> (63 - last)));
           if (stop) used = k + last + 1;
