@@ -61,8 +61,8 @@ ORBIT = 64
 MEASURED_TRAFFIC = {
     "sources_sha256": "6fc3a09132a20b8bff308a062dc9202b1b04e482c48376179e39b07949838ccc",
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
-        "cube1024_persp1920x1080/f32/composite/fixed": 2360897074,
-        "cube1024_persp1920x1080/f32/mip/voxel": 2453960766,
+        "cube1024_persp1920x1080/f32/composite/fixed": 2360906321,
+        "cube1024_persp1920x1080/f32/mip/voxel": 2453292633,
     },
 }
 KERNEL_SOURCES = ("bc_render.hip", "bc_types.h", "bc_kernels.h", "bc_df.h", "bc_e4m3.h")
