@@ -27,6 +27,7 @@ from __future__ import annotations
 import concurrent.futures as _cf
 import math
 import os
+import threading
 from dataclasses import dataclass
 
 import numpy as np
@@ -79,7 +80,9 @@ def _block_grid(dims):
     return tuple((d + GEN_BLOCK - 1) // GEN_BLOCK for d in dims)
 
 
-def _fill_block(recipe, sources, bidx, out, out_dtype):
+def block_values(recipe: CubeRecipe, sources, bidx: int):
+    """Float32 values of generation block ``bidx`` (x fastest over the block
+    grid), regenerated on its own; returns ((x0, y0, z0), array[z][y][x])."""
     nx, ny, nz = recipe.dims
     gbx, gby, _ = _block_grid(recipe.dims)
     bx = bidx % gbx
@@ -119,13 +122,21 @@ def _fill_block(recipe, sources, bidx, out, out_dtype):
         acc[sz, sy, sx] += a * (gz[sz][:, None, None] * gy[sy][None, :, None] * gx[sx][None, None, :])
     if acc is not None:
         block = (block.astype(np.float64) + acc).astype(np.float32)
+    return (x0, y0, z0), block
+
+
+def _fill_block(recipe, sources, bidx, out, out_dtype):
+    (x0, y0, z0), block = block_values(recipe, sources, bidx)
+    z1, y1, x1 = z0 + block.shape[0], y0 + block.shape[1], x0 + block.shape[2]
     out[z0:z1, y0:y1, x0:x1] = block.astype(out_dtype)
 
 
 def make_cube(recipe: CubeRecipe, out_dtype=np.float32, workers: int | None = None,
-              out: np.ndarray | None = None) -> np.ndarray:
+              out: np.ndarray | None = None, progress=None) -> np.ndarray:
     """Cube as ``array[z][y][x]`` (x fastest).  ``float16`` output is a
-    round-to-nearest-even cast of the float32 values."""
+    round-to-nearest-even cast of the float32 values.  ``progress(done,
+    total)``, if given, is called after each generation block (from the
+    generating threads)."""
     nx, ny, nz = recipe.dims
     if out is None:
         out = np.empty((nz, ny, nx), dtype=out_dtype)
@@ -134,13 +145,23 @@ def make_cube(recipe: CubeRecipe, out_dtype=np.float32, workers: int | None = No
     sources = draw_sources(recipe)
     if workers is None:
         workers = min(16, os.cpu_count() or 1)
+    done = [0]
+    lock = threading.Lock()
+
+    def fill(b):
+        _fill_block(recipe, sources, b, out, out_dtype)
+        if progress is not None:
+            with lock:
+                done[0] += 1
+                progress(done[0], nblocks)
+
     if workers <= 1 or nblocks == 1:
         for b in range(nblocks):
-            _fill_block(recipe, sources, b, out, out_dtype)
+            fill(b)
     else:
         # numpy releases the GIL in the random fill and the array arithmetic
         with _cf.ThreadPoolExecutor(max_workers=workers) as ex:
-            list(ex.map(lambda b: _fill_block(recipe, sources, b, out, out_dtype), range(nblocks)))
+            list(ex.map(fill, range(nblocks)))
     return out
 
 
