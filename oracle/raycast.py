@@ -293,20 +293,45 @@ class StoredBrick:
 _E4M3_LUT = encoders.e4m3_value(np.arange(256))
 
 
-def store_bricks(vol, bricks, storage="f32", ghost=1):
+class _NotStored:
+    """Values of a brick left out of ``store_bricks(..., only=...)``: reading
+    them is an error."""
+
+    def __init__(self, index):
+        self.index = index
+        self.shape = (1, 1, 1)
+
+    def __getitem__(self, key):
+        raise RuntimeError(f"brick {self.index} was not stored (outside only=)")
+
+
+def store_bricks(vol, bricks, storage="f32", ghost=1, only=None):
     """What each brick stores: f32 as given, f16 after an RNE cast, fp8 after
     per-brick affine e4m3 quantisation over its core + ghost values (ghosts
-    carry the owning brick's quantisation)."""
+    carry the owning brick's quantisation).
+
+    ``only``: if given, the indices of the bricks to store; every other brick
+    holds values that raise when read (a large cube checked at a few rays
+    needs only the bricks those rays cross).  f16 bricks are then stored as
+    their own ghosted regions, which equal the shared cube wherever the
+    brick's samples read it."""
     out = []
     if storage == "f32":
         shared = np.asarray(vol, dtype=np.float32)
         return [StoredBrick(b, shared, (0, 0, 0)) for b in bricks]
-    if storage == "f16":
+    if storage == "f16" and only is None:
         shared = encoders.f16_value(encoders.f16_bits(vol)).astype(np.float32)   # exact
         return [StoredBrick(b, shared, (0, 0, 0)) for b in bricks]
-    if storage != "fp8":
+    if storage not in ("f16", "fp8"):
         raise ValueError(storage)
     for b in bricks:
+        if only is not None and b.index not in only:
+            out.append(StoredBrick(b, _NotStored(b.index), (0, 0, 0)))
+            continue
+        if storage == "f16":
+            g = encoders.f16_value(encoders.f16_bits(ghosted_region(vol, b, ghost))).astype(np.float32)
+            out.append(StoredBrick(b, g, tuple(int(x) - ghost for x in b.lo)))
+            continue
         g = ghosted_region(vol, b, ghost).astype(np.float32)
         s, o = encoders.brick_scale_offset(float(g.min()), float(g.max()))
         codes = encoders.fp8_encode_brick(g, s, o)

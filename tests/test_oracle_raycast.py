@@ -430,6 +430,35 @@ def test_fp8_bricks_use_own_quantisation_and_fp16_is_exact_cast():
         assert b.origin == tuple(x - 1 for x in b.brick.lo)
 
 
+def test_storing_only_crossed_bricks_keeps_the_sampled_pixels():
+    """Storing only the bricks that the checked rays cross gives those pixels
+    as storing every brick does (FP16: the brick's own ghosted region instead
+    of the shared cube, so up to the rounding of the origin shift); a brick
+    left out raises when a ray reads it."""
+    rng = np.random.default_rng(21)
+    dims = (20, 18, 16)
+    vol = (rng.standard_normal(dims[::-1]) * 3).astype(np.float32)
+    tf = rc.TransferFunction(synth.random_tf(rng, 16, alpha_max=0.4), -6.0, 6.0)
+    cam = _cam(synth.orbit_view(dims, 7, kind="persp", width=24, height=20))
+    bricks = rc.brick_grid(dims, (8, 8, 8))
+    pix = np.array([[x, y] for x in range(9, 13) for y in range(8, 11)])
+    o, d = cam.rays(pix[:, 0], pix[:, 1])
+    crossed = set()
+    for b in bricks:
+        tb0, tb1 = rc.slab(o, d, tuple(float(x) for x in b.lo), tuple(float(x) for x in b.hi))
+        if np.any(tb0 < tb1):
+            crossed.add(b.index)
+    assert 0 < len(crossed) < len(bricks)
+    for storage in ("f16", "fp8"):
+        full = rc.render_bricked(rc.store_bricks(vol, bricks, storage), dims, cam, tf, 0.5, 0.95, pixels=pix)
+        part = rc.render_bricked(rc.store_bricks(vol, bricks, storage, only=crossed), dims, cam, tf, 0.5,
+                                 0.95, pixels=pix)
+        assert full.image[:, 3].max() > 0.05
+        assert np.max(np.abs(full.image - part.image)) <= 1e-12
+    with pytest.raises(RuntimeError, match="not stored"):
+        rc.render_bricked(rc.store_bricks(vol, bricks, "fp8", only=set()), dims, cam, tf, 0.5, 0.95, pixels=pix)
+
+
 def test_branch_enumeration_consistent_with_vectorised_path():
     """Rays without near ties give one branch equal to the vectorised result;
     an exact exit tie gives two branches that differ by one sample."""
