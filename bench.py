@@ -304,7 +304,15 @@ def main():
     t = time.perf_counter()
     vol = synth.make_cube(recipe, workers=min(16, os.cpu_count() or 1),
                           out_dtype=np.float16 if src_dtype == "f16" else np.float32)
-    vmin, vmax = float(vol.min()), float(vol.max())
+    if vol.dtype == np.float16:
+        # numpy reduces FP16 element by element; torch's threaded reduction
+        # gives the same (exact) extremes in seconds on a 27 GB cube
+        import torch
+        tv = torch.from_numpy(vol)
+        vmin, vmax = float(tv.min()), float(tv.max())
+        del tv
+    else:
+        vmin, vmax = float(vol.min()), float(vol.max())
     log(f"cube {recipe.dims} generated in {time.perf_counter() - t:.1f} s; range [{vmin:.3f}, {vmax:.3f}]")
     rgba = synth.ramp_tf(vmin, vmax)
     sets = view_sets(recipe, W, H, per_launch, args.frames)
