@@ -63,6 +63,9 @@ MEASURED_TRAFFIC = {
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
         "cube1024_persp1920x1080/f32/composite/fixed": 2360906321,
         "cube1024_persp1920x1080/f32/mip/voxel": 2453292633,
+        "cube1024_persp1920x1080/f16/composite/fixed": 1487578767,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 1008022383,
+        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 52033739477,
     },
 }
 KERNEL_SOURCES = ("bc_render.hip", "bc_types.h", "bc_kernels.h", "bc_df.h", "bc_e4m3.h")
