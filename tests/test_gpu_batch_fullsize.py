@@ -31,6 +31,9 @@ def batch_cube(request):
     capman = request.config.pluginmanager.getplugin("capturemanager")
 
     def say(m):   # progress lines, shown while the cube is generated
+        if capman is None:
+            print(m, flush=True)
+            return
         with capman.global_and_fixture_disabled():
             print(m, flush=True)
 
