@@ -179,7 +179,8 @@ def _ref_chunk(pix):
 
 
 def oracle_reference(vol, recipe, brick, view, rgba, vmin, vmax, n_px, workers, args):
-    """FP64 oracle on the FP32 cube at a seeded sample of hit pixels of one frame."""
+    """FP64 oracle on the source cube (FP32, or an FP16 source as it is) at a seeded
+    sample of hit pixels of one frame."""
     from oracle import raycast as rc
     dims = recipe.dims
     _CPU.update(stored=rc.store_bricks(vol, rc.brick_grid(dims, (brick,) * 3)), dims=dims,

@@ -317,7 +317,9 @@ def store_bricks(vol, bricks, storage="f32", ghost=1, only=None):
     brick's samples read it."""
     out = []
     if storage == "f32":
-        shared = np.asarray(vol, dtype=np.float32)
+        # an FP16 source is kept as it is: its values widen exactly when
+        # gathered, and a float32 copy of a large cube is not made
+        shared = vol if isinstance(vol, np.ndarray) and vol.dtype == np.float16 else np.asarray(vol, dtype=np.float32)
         return [StoredBrick(b, shared, (0, 0, 0)) for b in bricks]
     if storage == "f16" and only is None:
         shared = encoders.f16_value(encoders.f16_bits(vol)).astype(np.float32)   # exact

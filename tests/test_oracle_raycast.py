@@ -459,6 +459,22 @@ def test_storing_only_crossed_bricks_keeps_the_sampled_pixels():
         rc.render_bricked(rc.store_bricks(vol, bricks, "fp8", only=set()), dims, cam, tf, 0.5, 0.95, pixels=pix)
 
 
+def test_fp16_source_is_stored_without_a_copy_and_renders_as_its_float32_widening():
+    rng = np.random.default_rng(22)
+    dims = (12, 10, 9)
+    v16 = (rng.standard_normal(dims[::-1]) * 3).astype(np.float16)
+    bricks = rc.brick_grid(dims, (5, 4, 4))
+    s16 = rc.store_bricks(v16, bricks)
+    s32 = rc.store_bricks(v16.astype(np.float32), bricks)
+    assert s16[0].values is v16
+    tf = rc.TransferFunction(synth.random_tf(rng, 16, alpha_max=0.4), -6.0, 6.0)
+    cam = _cam(synth.orbit_view(dims, 3, kind="persp", width=16, height=14))
+    a = rc.render_bricked(s16, dims, cam, tf, 0.5, 0.95)
+    b = rc.render_bricked(s32, dims, cam, tf, 0.5, 0.95)
+    assert a.image[:, 3].max() > 0.05
+    assert np.array_equal(a.image, b.image)
+
+
 def test_branch_enumeration_consistent_with_vectorised_path():
     """Rays without near ties give one branch equal to the vectorised result;
     an exact exit tie gives two branches that differ by one sample."""
