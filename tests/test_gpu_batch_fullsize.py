@@ -5,9 +5,9 @@ cube (noise + 5000 sources, about 27 GB) from an FP16 source, stored FP16 in
 bench.py times for this workload, eager and replayed as a captured graph),
 against the FP64 oracle at sampled pixels of every view.
 
-FP16 storage of an FP16 source is an exact copy, so the oracle reads the host
-FP16 cube itself: each gathered value converts exactly to FP64, and no FP32 or
-FP64 copy of the cube is made.  The sampled pixels of each view are a block of
+FP16 storage of an FP16 source is an exact copy, so the oracle stores the host
+FP16 cube as it is: each gathered value converts exactly to FP64, and no FP32
+or FP64 copy of the cube is made.  The sampled pixels of each view are a block of
 neighbours (rays that share bricks and cells), pixels scattered over the
 image, and pixels whose rays miss the cube."""
 import time
@@ -62,9 +62,10 @@ def batch_cube(request):
     torch.cuda.empty_cache()
     bc.set_transfer_function(rgba, vmin, vmax)
     say(f"  batch cube: generated and loaded in {time.perf_counter() - t:.0f} s")
-    # every brick shares the FP16 cube (values exact in FP64), as FP16
-    # storage of the oracle's own bricking does
-    stored = [rc.StoredBrick(b, vol, (0, 0, 0)) for b in rc.brick_grid(dims, (BRICK,) * 3)]
+    # FP16 storage of an FP16 source holds exactly the source's values: the
+    # oracle stores the source as it is, shared by every brick
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (BRICK,) * 3))
+    assert stored[0].values is vol
     tf = rc.TransferFunction(rgba, vmin, vmax)
     yield dict(bc=bc, stored=stored, tf=tf, dims=dims, say=say)
     bc.close()
