@@ -59,12 +59,12 @@ ORBIT = 64
 # (the 64-frame orbit, twice).  Valid only for the kernel sources whose SHA-256
 # is recorded; any other source reports null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "6fc3a09132a20b8bff308a062dc9202b1b04e482c48376179e39b07949838ccc",
+    "sources_sha256": "7e59b42cabf510622c82cb5454ccafba5bc1845b2213816495467f61037da748",
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
         "cube1024_persp1920x1080/f32/composite/fixed": 2360906321,
         "cube1024_persp1920x1080/f32/mip/voxel": 2453292633,
         "cube1024_persp1920x1080/f16/composite/fixed": 1487578767,
-        "cube1024_persp1920x1080/fp8/composite/fixed": 1008022383,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 1003325781,
         "cube3000x3000x1500_f16_4views/f16/composite/fixed": 52033739477,
     },
 }

@@ -94,8 +94,13 @@ __device__ __forceinline__ void load_pair(__amdgpu_buffer_rsrc_t r, uint32_t ofs
     typedef float f2 __attribute__((ext_vector_type(2)));
     const uint32_t p = __builtin_amdgcn_raw_buffer_load_b16(r, ofs, 0, 0);
     const f2 v = __builtin_amdgcn_cvt_pk_f32_fp8((int)p, false);
-    a = __builtin_fmaf(v.x, s, o);
-    b = __builtin_fmaf(v.y, s, o);
+    if (FMT == 3) {   // the codes' values only: the caller applies scale and offset
+      a = v.x;
+      b = v.y;
+    } else {
+      a = __builtin_fmaf(v.x, s, o);
+      b = __builtin_fmaf(v.y, s, o);
+    }
   }
 }
 
@@ -430,6 +435,12 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
       const uint32_t n_vox = (uint32_t)br.mb[0] * (uint32_t)br.mb[1] * (uint32_t)br.mb[2] * BC_MB_ELEMS;
       const __amdgpu_buffer_rsrc_t pool = make_rsrc(static_cast<const char*>(f.pool) + br.offset * esz, n_vox * esz);
       const float s_q = br.scale, o_q = br.offs;
+      // FP8 compositing: interpolation is linear, so the brick's scale and
+      // offset move from the 8 decoded voxels into the table index (one
+      // multiply-add per sample); MIP compares decoded values with the
+      // brick maximum and decodes each voxel
+      constexpr bool FOLD = FMT == 2 && OP == 0;
+      const float tsc = FOLD ? tf_scale * s_q : tf_scale, tbi = FOLD ? __builtin_fmaf(o_q, tf_scale, tf_bias) : tf_bias;
       // byte steps to the +y/+z neighbour: inside a micro-block, or across
       // into the next one (from its last row or slice)
       constexpr uint32_t sh = FMT == 0 ? 2 : (FMT == 1 ? 1 : 0);
@@ -534,10 +545,10 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
                 const uint32_t dy = ry == 3 ? dyb : (BC_ROW << sh);
                 const uint32_t dz = rz == 3 ? dzb : ((4u * BC_ROW) << sh);
                 const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
-                load_pair<FMT>(pool, a000, s_q, o_q, cv[0], cv[1]);
-                load_pair<FMT>(pool, a010, s_q, o_q, cv[2], cv[3]);
-                load_pair<FMT>(pool, a001, s_q, o_q, cv[4], cv[5]);
-                load_pair<FMT>(pool, a011, s_q, o_q, cv[6], cv[7]);
+                load_pair<FOLD ? 3 : FMT>(pool, a000, s_q, o_q, cv[0], cv[1]);
+                load_pair<FOLD ? 3 : FMT>(pool, a010, s_q, o_q, cv[2], cv[3]);
+                load_pair<FOLD ? 3 : FMT>(pool, a001, s_q, o_q, cv[4], cv[5]);
+                load_pair<FOLD ? 3 : FMT>(pool, a011, s_q, o_q, cv[6], cv[7]);
                 cell_ofs = a000;
               }
               const float c00 = __builtin_fmaf(wx, cv[1] - cv[0], cv[0]);
@@ -557,7 +568,7 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
                 continue;
               }
               // clamp to [0, K-1] (the median of three, exact)
-              const float xt = __builtin_amdgcn_fmed3f(__builtin_fmaf(val, tf_scale, tf_bias), 0.0f, kmax_f);
+              const float xt = __builtin_amdgcn_fmed3f(__builtin_fmaf(val, tsc, tbi), 0.0f, kmax_f);
               // (the table in LDS has an entry K-1 with a zero difference)
               const int it = TF_LDS ? (int)xt : min((int)xt, K - 2);
               const float ft = TF_LDS ? __builtin_amdgcn_fractf(xt) : xt - (float)it;
