@@ -25,8 +25,10 @@ activation) and its weights are rounded to bfloat16, products are accumulated
 in FP32 with the bias, ReLU is applied and the result is rounded to bfloat16
 for the next layer; the third layer's output, the pixel shuffle and the
 bilinear residual stay FP32.  ``forward(..., bf16=True)`` applies the same
-roundings (round to nearest even) so that the oracle and the device differ
-only by FP32 accumulation order.
+roundings (round to nearest even), and ``backward(..., bf16=True)`` those of
+the backward pass (the output gradient and both hidden-layer gradients
+rounded to bfloat16), so that the oracle and the device differ only by FP32
+accumulation order.
 
 Flat parameter layout (FP32 master copy): W1, b1, W2, b2, W3, b3, each
 weight tensor [out][in][3][3] row-major.
@@ -171,16 +173,27 @@ def loss(out, target):
     return float(np.mean(d * d))
 
 
-def backward(cache, out, target):
+def backward(cache, out, target, bf16=False, count=None):
     """Gradient of the MSE loss with respect to the flat parameters (in the
-    order of split_params).  The residual bilinear path has no parameters."""
-    g = 2.0 * (out - np.asarray(target, np.float64)) / out.size
-    gy = pixel_unshuffle2(g)
+    order of split_params).  The residual bilinear path has no parameters.
+
+    ``count`` is the number of elements the mean runs over (default: this
+    image's; a batch passes its total and sums the per-image results).
+    ``bf16=True`` is the precision reading of the device's backward pass: the
+    gradient of the last layer's output and the masked gradients of both hidden
+    layers are rounded to bfloat16 (round to nearest even) before they enter
+    the next convolution, the weight gradients and the bias sums; the weights
+    and activations are the BF16-rounded ones of the forward cache.  The oracle
+    and the device then differ only by FP32 accumulation order."""
+    q = bf16_round if bf16 else (lambda t: t)
+    n = out.size if count is None else count
+    g = 2.0 * (out - np.asarray(target, np.float64)) / n
+    gy = q(pixel_unshuffle2(g))
     w1, w2, w3 = cache["w"]
     ga2, gw3, gb3 = conv3x3_backward(cache["a2"], w3, gy)
-    gz2 = ga2 * (cache["z2"] > 0)
+    gz2 = q(ga2 * (cache["z2"] > 0))
     ga1, gw2, gb2 = conv3x3_backward(cache["a1"], w2, gz2)
-    gz1 = ga1 * (cache["z1"] > 0)
+    gz1 = q(ga1 * (cache["z1"] > 0))
     _, gw1, gb1 = conv3x3_backward(cache["x"], w1, gz1)
     return np.concatenate([gw1.ravel(), gb1, gw2.ravel(), gb2, gw3.ravel(), gb3])
 

@@ -39,6 +39,7 @@ C8  Sort-last: F <- F + (1 - F_a) S_b over bricks in visibility order.
 """
 from __future__ import annotations
 
+import itertools
 import math
 from dataclasses import dataclass, field
 
@@ -51,7 +52,8 @@ from . import encoders
 # get every branch evaluated.
 DELTA_T = 1e-6
 DELTA_ALPHA = 1e-4
-MAX_BRANCHES = 16
+MAX_CONFIGS = 256        # sample-membership configurations of one ray
+MAX_BRANCHES = 1 << 14   # distinct results of one ray
 
 
 # ---------------------------------------------------------------------- camera
@@ -368,7 +370,7 @@ class RenderResult:
     image: np.ndarray                 # (R, 4) premultiplied RGBA per requested pixel
     tie: np.ndarray                   # (R,) a discontinuous decision was near its threshold
     branches: dict                    # ray index -> list of (4,) alternative results
-    overflow: np.ndarray              # (R,) more branches than MAX_BRANCHES
+    overflow: np.ndarray              # (R,) branch list incomplete (MAX_CONFIGS / MAX_BRANCHES exceeded)
     samples: np.ndarray               # (R,) samples composited (up to termination)
     order: list | None = None
     footprint: dict | None = None     # brick index -> bool (R,) (>= 1 sample in the brick)
@@ -462,12 +464,14 @@ def render_bricked(stored, dims, cam: Camera, tf: TransferFunction, dt: float, t
             j0, j1, j0u, j1u, tb0, tb1, hit_b = _brick_sample_range(t_in, n, dt, o, d, sb.brick)
             cnt = j1 - j0
             foot[bi][s:e] = cnt > 0
+            # (a brick the ray grazes, entered in FP64 or nearly, counts too)
+            live = tb0 < tb1 + 2.0 * DELTA_T
             for tb, cand in ((tb0, (j0u - 1, j0u)), (tb1, (j1u - 1, j1u))):
                 for jj in cand:
                     tj = t_in + (jj + 0.5) * dt
                     with np.errstate(invalid="ignore"):
                         near = np.abs(tj - tb) < DELTA_T
-                    tie[s:e] |= (hit_b & np.isfinite(tb) & (jj >= 0) & (jj < n)
+                    tie[s:e] |= (live & np.isfinite(tb) & (jj >= 0) & (jj < n)
                                  & near)
             J = int(cnt.max()) if len(cnt) else 0
             if J == 0:
@@ -499,95 +503,152 @@ def render_bricked(stored, dims, cam: Camera, tf: TransferFunction, dt: float, t
 
 
 # ------------------------------------------------- per-ray branch enumeration
-def _march_ray(stored_sorted, dims, o, d, table, tf, dt, tau, forced):
-    """One ray of R_bricked with some near-tie decisions forced.  Returns the
-    pixel and the near-tie decisions met in ray order with their defaults."""
-    o1, d1 = o[None, :], d[None, :]
-    t_in, t_out, hit = global_interval(o1, d1, dims)
+# A near tie is a discontinuous decision whose FP64 margin is below DELTA_T
+# (sample times against the cube exit or a brick face) or DELTA_ALPHA (the
+# opacity of a brick's ray against tau).  A ray's reachable results are
+# enumerated in two layers:
+#   membership  every sample near a face may belong to any brick whose interval
+#               it is near (one owner per sample, as the bricks partition the
+#               ray), and a sample near the cube exit may be taken or not;
+#               the combinations are the ray's configurations;
+#   termination per brick, opacity never decreases along its samples, so the
+#               reachable ends of its ray are: after each sample whose opacity
+#               lies within DELTA_ALPHA of tau, after the first sample at or
+#               above tau + DELTA_ALPHA, and after its last sample if none is;
+#               that is linear in the number of samples, with no cap.
+# Sub-images are folded over the bricks in visibility order (C8); results that
+# are bit-identical are kept once (a transparent sample leaves a brick's
+# sub-image unchanged, so a long transparent run near tau adds nothing).
+def _ray_chord(dims, o, d, dt):
+    t_in, t_out, hit = global_interval(o[None, :], d[None, :], dims)
     t_in, t_out, hit = float(t_in[0]), float(t_out[0]), bool(hit[0])
-    ties = []
     if not hit:
-        return np.zeros(4), ties
+        return t_in, t_out, False, 0
     n = int(sample_count(np.array([t_in]), np.array([t_out]), dt, np.array([True]))[0])
-    # exit decision: the last included sample and the first excluded one
-    n0 = n
-    for jj, default in ((n0 - 1, True), (n0, False)):
-        tj = t_in + (jj + 0.5) * dt
-        if jj >= 0 and abs(tj - t_out) < DELTA_T:
-            key = ("exit", jj)
-            ties.append((key, default))
-            inc = forced.get(key, default)
-            if inc != default:
-                n = jj + 1 if inc else jj
-    F = np.zeros(4)
-    for sb in stored_sorted:
+    return t_in, t_out, True, n
+
+
+def _sample_owner_options(stored_sorted, o, d, t_in, dt, n_max):
+    """For samples j < n_max: the owner options (tuples of positions in
+    stored_sorted), the FP64 default first.  A sample inside exactly one brick
+    and near no face has that brick alone."""
+    tj = t_in + (np.arange(n_max) + 0.5) * dt
+    claim = [[] for _ in range(n_max)]
+    near = [[] for _ in range(n_max)]
+    o1, d1 = o[None, :], d[None, :]
+    for pos, sb in enumerate(stored_sorted):
         br = sb.brick
         tb0, tb1 = slab(o1, d1, tuple(float(x) for x in br.lo), tuple(float(x) for x in br.hi))
         tb0, tb1 = float(tb0[0]), float(tb1[0])
-        if not tb0 < tb1:
+        if not tb0 < tb1 + 2.0 * DELTA_T:
             continue
-        members = []
-        for j in range(n):
-            tj = t_in + (j + 0.5) * dt
-            inside = tb0 <= tj < tb1
-            near = (abs(tj - tb0) < DELTA_T) or (abs(tj - tb1) < DELTA_T)
-            if near:
-                key = ("face", br.index, j)
-                ties.append((key, inside))
-                inside = forced.get(key, inside)
-            if inside:
-                members.append(j)
-        if not members:
-            continue
-        ts = np.array([t_in + (j + 0.5) * dt for j in members])
-        p = o[None, :] + ts[:, None] * d[None, :]
-        v = trilinear(sb.values, p, origin=sb.origin, decode=sb.decode)
-        c = tf.lookup(table, v)
-        S = np.zeros(4)
-        for m, j in enumerate(members):
-            S = S + (1.0 - S[3]) * c[m]
-            stop = S[3] >= tau
-            if abs(S[3] - tau) < DELTA_ALPHA:
-                key = ("ert", br.index, j)
-                ties.append((key, stop))
-                stop = forced.get(key, stop)
-            if stop:
-                break
-        F = over(F, S)
-    return F, ties
+        inside = (tb0 <= tj) & (tj < tb1)
+        with np.errstate(invalid="ignore"):
+            close = (np.abs(tj - tb0) < DELTA_T) | (np.abs(tj - tb1) < DELTA_T)
+        for j in np.nonzero(inside)[0]:
+            claim[j].append(pos)
+        for j in np.nonzero(close)[0]:
+            near[j].append(pos)
+    options = []
+    for j in range(n_max):
+        default = tuple(claim[j])
+        opts = [default]
+        if near[j]:
+            for pos in sorted(set(claim[j]) | set(near[j])):
+                if (pos,) not in opts:
+                    opts.append((pos,))
+        options.append(opts)
+    return options
+
+
+def _brick_results(sb, o, d, t_in, dt, members, table, tf, tau):
+    """Distinct sub-images of one brick over its reachable termination points."""
+    ts = t_in + (np.asarray(members, dtype=np.float64) + 0.5) * dt
+    p = o[None, :] + ts[:, None] * d[None, :]
+    v = trilinear(sb.values, p, origin=sb.origin, decode=sb.decode)
+    c = tf.lookup(table, v)
+    S = np.zeros(4)
+    prefix = []
+    for m in range(len(members)):
+        S = S + (1.0 - S[3]) * c[m]
+        prefix.append(S)
+    ends = []
+    for k, Sk in enumerate(prefix):
+        if abs(Sk[3] - tau) < DELTA_ALPHA:
+            ends.append(k)
+        elif Sk[3] >= tau + DELTA_ALPHA:
+            ends.append(k)
+            break
+    else:
+        ends.append(len(prefix) - 1)
+    out = {}
+    for k in ends:
+        out.setdefault(tuple(prefix[k].tolist()), prefix[k])
+    return list(out.values())
 
 
 def ray_branches(stored, dims, cam, tf, dt, tau, px, py):
-    """All results of one ray over the near-tie decisions it meets (each such
-    decision taken both ways), at most MAX_BRANCHES.  Returns (list, overflow)."""
+    """Every result one ray of R_bricked can take over its near-tie decisions.
+    Returns (list of (4,) results, overflow); overflow is set when the ray has
+    more than MAX_CONFIGS membership configurations or more than MAX_BRANCHES
+    distinct results (the list is then incomplete)."""
     order, _ = visibility_order([sb.brick for sb in stored], cam)
     by_index = {sb.brick.index: sb for sb in stored}
     stored_sorted = [by_index[i] for i in order]
     o, d = cam.rays(np.array([px]), np.array([py]))
     o, d = o[0], d[0]
+    t_in, t_out, hit, n0 = _ray_chord(dims, o, d, dt)
+    if not hit:
+        return [np.zeros(4)], False
+    # exit decision: the last included sample and the first excluded one
+    counts = [n0]
+    for jj, inc in ((n0 - 1, n0 - 1), (n0, n0 + 1)):
+        if jj >= 0 and abs(t_in + (jj + 0.5) * dt - t_out) < DELTA_T and inc not in counts:
+            counts.append(inc)
+    n_max = max(counts)
+    options = _sample_owner_options(stored_sorted, o, d, t_in, dt, n_max)
+    tie_js = [j for j in range(n_max) if len(options[j]) > 1]
+    n_conf = len(counts)
+    for j in tie_js:
+        n_conf *= len(options[j])
+    if n_conf > MAX_CONFIGS:
+        return [], True
     table = tf.table(dt)
-    results, seen = [], set()
-    stack = [dict()]
+    cache = {}
+    results = {}
     overflow = False
-    while stack:
-        forced = stack.pop()
-        key = tuple(sorted(forced.items()))
-        if key in seen:
-            continue
-        seen.add(key)
-        if len(results) >= MAX_BRANCHES:
+    for n in counts:
+        js = [j for j in tie_js if j < n]
+        for choice in itertools.product(*[options[j] for j in js]):
+            owner = {j: options[j][0] for j in range(n)}
+            owner.update(zip(js, choice))
+            members = [[] for _ in stored_sorted]
+            for j in range(n):
+                for pos in owner[j]:
+                    members[pos].append(j)
+            partial = {(0.0, 0.0, 0.0, 0.0): np.zeros(4)}
+            for pos, mem in enumerate(members):
+                if not mem:
+                    continue
+                key = (pos, tuple(mem))
+                if key not in cache:
+                    cache[key] = _brick_results(stored_sorted[pos], o, d, t_in, dt, mem, table, tf, tau)
+                nxt = {}
+                for F in partial.values():
+                    for S in cache[key]:
+                        G = over(F, S)
+                        nxt.setdefault(tuple(G.tolist()), G)
+                if len(nxt) > MAX_BRANCHES:
+                    overflow = True
+                    break
+                partial = nxt
+            if overflow:
+                break
+            results.update(partial)
+        if overflow or len(results) > MAX_BRANCHES:
             overflow = True
             break
-        F, ties = _march_ray(stored_sorted, dims, o, d, table, tf, dt, tau, forced)
-        results.append(F)
-        fixed = dict(forced)
-        for k, default in ties:
-            if k not in forced:
-                alt = dict(fixed)
-                alt[k] = not default
-                stack.append(alt)
-                fixed[k] = default
-    return results, overflow
+    return list(results.values()), overflow
 
 
 # ------------------------------------------------------------ image helpers

@@ -6,7 +6,8 @@ Tolerances follow from the arithmetic: inference differs from the oracle only
 by FP32 accumulation order (and the rare BF16 rounding flip of an activation
 that this causes), so the relative Frobenius error is held to 1e-3; the
 backward pass also rounds the output gradient and the hidden-layer gradients
-to BF16 (relative step 2^-8), so gradients are held to 2e-2."""
+to BF16, and the oracle's backward applies the same roundings, so gradients
+are held to 1e-3 per parameter block as well."""
 import numpy as np
 import pytest
 
@@ -81,12 +82,14 @@ def test_gradients_match_oracle(caster):
     loss_ref = 0.0
     for i in range(n):
         out, cache = cnn.forward(p.astype(np.float64), x[i], bf16=True)
-        g_ref += cnn.backward(cache, out, t[i]) / n
+        g_ref += cnn.backward(cache, out, t[i], bf16=True, count=n * out.size)
         loss_ref += cnn.loss(out, t[i]) / n
     assert abs(loss_gpu - loss_ref) <= 1e-3 * loss_ref
     blocks = [(0, 1152), (1152, 1184), (1184, 10400), (10400, 10432), (10432, 15040), (15040, 15056)]
     for lo, hi in blocks:
-        assert _rel(g_gpu[lo:hi], g_ref[lo:hi]) <= 2e-2, (lo, hi, _rel(g_gpu[lo:hi], g_ref[lo:hi]))
+        rel = _rel(g_gpu[lo:hi], g_ref[lo:hi])
+        print(f"parameters {lo}..{hi}: relative Frobenius error {rel:.3g}")
+        assert rel <= 1e-3, (lo, hi, rel)
 
 
 def test_adam_step_and_resume_bit_identical(caster):

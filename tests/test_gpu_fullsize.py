@@ -12,7 +12,7 @@ from oracle import mip
 from oracle import raycast as rc
 from paper_1205_0282_amd import binding, synth
 
-from gpu_util import TOL, cam_of
+from gpu_util import TOL, cam_of, compare, compare_mip
 
 pytestmark = pytest.mark.gpu
 
@@ -56,9 +56,8 @@ def test_cube1024_frame_sampled_pixels(cube1024):
         cam = cam_of(v)
         pix = _pixels(cam, dims, 100 + frame)
         res = rc.render_bricked(stored, dims, cam, tf, 0.5, 0.99, pixels=pix)
-        err = rc.max_abs_with_branches(img[pix[:, 1], pix[:, 0]], res)
-        print(f"frame {frame}: max err {err.max():.3g} over {len(pix)} pixels, {int(res.tie.sum())} near-tie rays")
-        assert err[~res.overflow].max() <= TOL
+        err, _, _ = compare(img[pix[:, 1], pix[:, 0]], res, f"frame {frame}")
+        assert err <= TOL
         assert res.image[:, 3].max() > 0.1
 
 
@@ -73,10 +72,7 @@ def test_cube1024_mip_per_voxel_sampled_pixels(cube1024):
             cam = cam_of(v)
             pix = _pixels(cam, dims, 200 + frame)
             res = mip.render_mip_bricked(stored, dims, cam, tf, "voxel", pixels=pix)
-            err = mip.max_abs_with_branches(img[pix[:, 1], pix[:, 0]], res)
-            print(f"mip frame {frame}: max err {err.max():.3g} over {len(pix)} pixels, "
-                  f"{int(res.tie.sum())} near-tie rays")
-            assert err.max() <= TOL
+            assert compare_mip(img[pix[:, 1], pix[:, 0]], res, f"mip frame {frame}") <= TOL
             assert np.unique(res.image[res.samples > 0, 0]).size > 20
     finally:
         bc.set_operator("composite", "fixed")
@@ -133,9 +129,7 @@ def test_cube1024_stored_forms_sampled_pixels(cube1024, storage):
             crossed.add(b.index)
     stored = rc.store_bricks(vol, bricks, storage, only=crossed)
     res = rc.render_bricked(stored, dims, cam, tf, 0.5, 0.99, pixels=pix)
-    err = rc.max_abs_with_branches(img[pix[:, 1], pix[:, 0]], res)
-    print(f"{storage}: max err {err.max():.3g} over {len(pix)} pixels, {len(crossed)} of {len(bricks)} "
-          f"bricks encoded, {int(res.tie.sum())} near-tie rays")
-    assert err[~res.overflow].max() <= TOL
+    err, _, _ = compare(img[pix[:, 1], pix[:, 0]], res, f"{storage}, {len(crossed)} of {len(bricks)} bricks encoded")
+    assert err <= TOL
     assert res.image[:, 3].max() > 0.1
     assert np.all(img[misses[:, 1], misses[:, 0]] == 0.0)

@@ -10,7 +10,7 @@ from oracle import encoders
 from oracle import raycast as rc
 from paper_1205_0282_amd import binding, synth
 
-from gpu_util import TOL, cam_of, compare, gpu_render
+from gpu_util import TOL, cam_of, compare, compare_mip, gpu_render
 
 pytestmark = pytest.mark.gpu
 
@@ -35,10 +35,8 @@ def test_small_plain_full_frame(small_cube, tau):
     tf = rc.TransferFunction(rgba, vmin, vmax)
     stored = rc.store_bricks(vol, rc.brick_grid(vol.shape[::-1], (64, 64, 64)))
     res = rc.render_bricked(stored, vol.shape[::-1], cam_of(v), tf, 0.5, tau)
-    err, n_tie, n_ovf = compare(img[0].reshape(-1, 4), res)
-    print(f"max err {err:.3g}, near-tie rays {n_tie}, overflow {n_ovf}")
+    err, n_tie, n_ovf = compare(img[0].reshape(-1, 4), res, f"128^3 tau {tau}")
     assert err <= TOL
-    assert n_ovf == 0
     assert res.image[:, 3].max() > 0.5           # the frame is not trivially empty
     assert np.array_equal(bc.visibility_order(0), np.asarray(res.order, np.int32))
     rects = bc.rects(0)
@@ -67,7 +65,7 @@ def test_brute_force_cubes_four_views(n, brick, kind, seed):
     stored = rc.store_bricks(vol, rc.brick_grid(dims, brick))
     for i, v in enumerate(views):
         res = rc.render_bricked(stored, dims, cam_of(v), tf, 0.37, 0.8)
-        err, n_tie, n_ovf = compare(img[i].reshape(-1, 4), res)
+        err, n_tie, n_ovf = compare(img[i].reshape(-1, 4), res, f"view {i}")
         assert err <= TOL, (i, err)
         assert np.array_equal(bc.visibility_order(i), np.asarray(res.order, np.int32))
     bc.close()
@@ -113,7 +111,7 @@ def test_precision_forms_match_oracle_on_stored_values(small_cube, storage):
     tf = rc.TransferFunction(rgba, vmin, vmax)
     stored = rc.store_bricks(vol, rc.brick_grid(vol.shape[::-1], (64, 64, 64)), storage)
     res = rc.render_bricked(stored, vol.shape[::-1], cam_of(v), tf, 0.5, 0.99)
-    err, n_tie, _ = compare(img[0].reshape(-1, 4), res)
+    err, n_tie, _ = compare(img[0].reshape(-1, 4), res, storage)
     assert err <= TOL, err
     # and the error of the storage form against FP32 data, reported
     ref = rc.render_bricked(rc.store_bricks(vol, rc.brick_grid(vol.shape[::-1], (64, 64, 64))),
@@ -134,7 +132,7 @@ def test_uneven_bricks_host_and_device_loads_agree():
     assert np.array_equal(a, b)
     tf = rc.TransferFunction(rgba, vmin, vmax)
     res = rc.render_bricked(rc.store_bricks(vol, rc.brick_grid(dims, (32, 32, 32))), dims, cam_of(v), tf, 0.5, 0.99)
-    err, _, _ = compare(a[0].reshape(-1, 4), res)
+    err, _, _ = compare(a[0].reshape(-1, 4), res, "uneven bricks")
     assert err <= TOL
 
 
@@ -227,7 +225,7 @@ def test_fp8_decode_of_every_code():
     bc.close()
     stored = rc.store_bricks(vol, rc.brick_grid(dims, (16, 16, 2)), "fp8")
     res = rc.render_bricked(stored, dims, cam_of(v), rc.TransferFunction(rgba, -0.03, 0.03), 1.0, 1.0)
-    err, _, _ = compare(img[0].reshape(-1, 4), res)
+    err, _, _ = compare(img[0].reshape(-1, 4), res, "fp8 subnormal codes")
     assert err <= TOL, err
     # the subnormal codes matter: decoding them as zero changes the oracle image
     flushed = vol.copy()
@@ -298,12 +296,12 @@ def test_xcd_queues_and_chunks_do_not_change_the_image(small_cube):
     tf = rc.TransferFunction(rgba, vmin, vmax)
     stored = rc.store_bricks(vol, rc.brick_grid(vol.shape[::-1], (40, 48, 56)))
     res = rc.render_bricked(stored, vol.shape[::-1], cam_of(views[0]), tf, 0.5, 0.99)
-    err, _, _ = compare(ref[64][0].reshape(-1, 4), res)
+    err, _, _ = compare(ref[64][0].reshape(-1, 4), res, "xcd queues and chunks")
     assert err <= TOL
 
 
 @pytest.mark.parametrize("kind", ["persp", "ortho"])
-def test_thin_edge_bricks_like_table1_shapes(kind, monkeypatch):
+def test_thin_edge_bricks_like_table1_shapes(kind):
     """The paper's cube shapes split into 256^3 bricks leave thin edge bricks
     (1025 = 4 x 256 + 1 for the HIPASS cube).  A cube of 300 x 260 x 257 in
     128^3 bricks has edge bricks 44, 4 and 1 voxels thick: compositing and
@@ -311,11 +309,9 @@ def test_thin_edge_bricks_like_table1_shapes(kind, monkeypatch):
 
     A few rays of this view end with opacity just under the termination
     threshold for dozens of nearly transparent samples, each an early-
-    termination near-tie (stop there or go on); the branches differ by less
-    than 1e-9 but number a few hundred, so the oracle enumerates up to 4096
-    per ray here instead of giving up at its default cap."""
+    termination near-tie (stop there or go on); the oracle lists such a ray's
+    reachable ends linearly, so every ray is compared."""
     from oracle import mip
-    monkeypatch.setattr(rc, "MAX_BRANCHES", 4096)
     dims = (300, 260, 257)
     recipe = synth.CubeRecipe(dims, seed=21, n_sources=60, sigma_lo=4.0, sigma_hi=12.0)
     vol = synth.make_cube(recipe, workers=8)
@@ -325,13 +321,12 @@ def test_thin_edge_bricks_like_table1_shapes(kind, monkeypatch):
     tf = rc.TransferFunction(rgba, vmin, vmax)
     img = gpu_render(vol, (128, 128, 128), [v], rgba, vmin, vmax)
     res = rc.render_bricked(stored, dims, cam_of(v), tf, 0.5, 0.99)
-    err, _, n_ovf = compare(img[0].reshape(-1, 4), res)
-    assert err <= TOL and n_ovf == 0
+    err, _, n_ovf = compare(img[0].reshape(-1, 4), res, f"thin edge bricks {kind}")
+    assert err <= TOL
     assert res.image[:, 3].max() > 0.3
     img = gpu_render(vol, (128, 128, 128), [v], rgba, vmin, vmax, op=("mip", "voxel"))
     res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, "voxel")
-    err = mip.max_abs_with_branches(img[0].reshape(-1, 4), res)
-    assert err.max() <= TOL
+    assert compare_mip(img[0].reshape(-1, 4), res, f"thin edge bricks {kind} mip") <= TOL
 
 
 def test_more_than_64_bricks_per_block_of_tiles():
@@ -357,8 +352,8 @@ def test_more_than_64_bricks_per_block_of_tiles():
             most = max(most, int(meet.sum()))
     assert most > 64
     res = rc.render_bricked(stored, dims, cam_of(v), tf, 0.5, 0.99)
-    err, _, n_ovf = compare(img[0].reshape(-1, 4), res)
-    assert err <= TOL and n_ovf == 0
+    err, _, n_ovf = compare(img[0].reshape(-1, 4), res, "4096 bricks")
+    assert err <= TOL
     assert res.image[:, 3].max() > 0.3
     img = gpu_render(vol, (4, 4, 4), [v], rgba, vmin, vmax, op=("mip", "voxel"))
     res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, "voxel")
@@ -386,11 +381,55 @@ def test_smallest_cubes_bricks_and_frames(dims, brick):
     for v in views:
         img = gpu_render(vol, brick, [v], rgba, -1.0, 1.0)
         res = rc.render_bricked(stored, dims, cam_of(v), tf, v.step, v.ert)
-        err, _, n_ovf = compare(img[0].reshape(-1, 4), res)
-        assert err <= TOL and n_ovf == 0, (v.width, v.height, err)
+        err, _, n_ovf = compare(img[0].reshape(-1, 4), res, f"{dims} {v.width}x{v.height}")
+        assert err <= TOL, (v.width, v.height, err)
         lit += int(res.image[:, 3].max() > 0.2)
     assert lit >= 3
     v = views[2]
     img = gpu_render(vol, brick, [v], rgba, -1.0, 1.0, op=("mip", "voxel"))
     res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, "voxel")
     assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
+
+
+def _two_entry_tf(rgb, alpha):
+    return np.array([[0.0, 0.0, 0.0, 0.0], list(rgb) + [alpha]], np.float32)
+
+
+def test_constructed_exact_ties_match_an_enumerated_result():
+    """The oracle's exact-tie constructions rendered by the GPU: a sample on
+    the face between two FP8 bricks with different scale and offset (two
+    reachable pixels), opacity reaching tau exactly at a brick's second sample
+    (the GPU stops there, as FP32 reaches 3/4 exactly), and opacity held
+    within the tie margin of tau over 148 transparent samples."""
+    # face tie between FP8 bricks
+    dims = (2, 2, 6)
+    zcol = np.array([0.0, 1.0, 3.0, 2.0, 0.5, 0.25], np.float32)
+    vol = np.ascontiguousarray(np.broadcast_to(zcol[:, None, None], (6, 2, 2)))
+    rgba = _two_entry_tf((1.0, 0.5, 0.25), 0.75)
+    v = synth.axis_view(dims, "z", 2, 2, step=2.0, ert=1.0)
+    img = gpu_render(vol, (2, 2, 3), [v], rgba, 0.0, 4.0, storage="fp8", dt_ref=2.0)
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (2, 2, 3)), "fp8")
+    res = rc.render_bricked(stored, dims, cam_of(v), rc.TransferFunction(rgba, 0.0, 4.0, 2.0), 2.0, 1.0)
+    assert all(len(res.branches[r]) == 2 for r in range(4))
+    err, _, _ = compare(img[0].reshape(-1, 4), res, "fp8 face tie")
+    assert err <= TOL
+    # exact termination tie: the FP32 opacity is 0.5, then 0.75 = tau
+    dims = (1, 1, 8)
+    vol = np.ones((8, 1, 1), np.float32)
+    rgba = _two_entry_tf((0.75, 0.5, 0.25), 0.5)
+    v = synth.axis_view(dims, "z", 1, 1, step=1.0, ert=0.75)
+    img = gpu_render(vol, (1, 1, 4), [v], rgba, 0.0, 1.0)
+    assert np.array_equal(img[0, 0, 0], np.array([0.75, 0.5, 0.25, 1.0], np.float32) * 0.9375)
+    # a long run of transparent samples within the tie margin of tau
+    dims = (1, 1, 400)
+    col = np.zeros(400, np.float32)
+    col[0:2] = 1.0
+    col[150:] = 1.0
+    vol = col.reshape(400, 1, 1)
+    tau = 0.75 + 2.0 ** -15
+    v = synth.axis_view(dims, "z", 1, 1, step=1.0, ert=tau)
+    img = gpu_render(vol, (1, 1, 200), [v], rgba, 0.0, 1.0)
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (1, 1, 200)))
+    res = rc.render_bricked(stored, dims, cam_of(v), rc.TransferFunction(rgba, 0.0, 1.0), 1.0, tau)
+    err, _, _ = compare(img[0].reshape(-1, 4), res, "transparent run at tau")
+    assert err <= TOL

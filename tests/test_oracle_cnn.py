@@ -121,3 +121,40 @@ def test_zero_last_layer_gives_bilinear_output():
     x = _rng(9).uniform(0, 1, (4, 5, 4))
     out, _ = cnn.forward(p, x)
     assert np.allclose(out, cnn.bilinear2(x), atol=1e-15)
+
+
+def test_bf16_backward_is_the_exact_gradient_up_to_bf16_steps():
+    """The BF16 reading of the backward pass stays within the rounding it
+    models (relative step 2^-8 per rounded operand, three in series at the
+    first layer) of the exact gradient of the same forward pass, and does round
+    (it is not the exact gradient)."""
+    rng = _rng(21)
+    p = cnn.init_params(22).astype(np.float64)
+    p[cnn.N_PARAMS - 16:] = rng.standard_normal(16) * 0.1
+    x = rng.uniform(0, 1, (7, 9, 4))
+    t = rng.uniform(0, 1, (14, 18, 4))
+    out, cache = cnn.forward(p, x, bf16=True)
+    g64 = cnn.backward(cache, out, t)
+    g16 = cnn.backward(cache, out, t, bf16=True)
+    blocks = [(0, 1152), (1152, 1184), (1184, 10400), (10400, 10432), (10432, 15040), (15040, 15056)]
+    for lo, hi in blocks:
+        rel = np.linalg.norm(g16[lo:hi] - g64[lo:hi]) / np.linalg.norm(g64[lo:hi])
+        assert 0.0 < rel <= 3 * 2.0 ** -8, (lo, hi, rel)
+
+
+def test_bf16_backward_last_layer_exact_when_output_gradient_is_representable():
+    """With an output gradient whose every element is a power of two (exact in
+    bfloat16) the last layer's weight and bias gradients of the BF16 reading
+    equal the exact ones (to FP64 rounding): nothing else is rounded before
+    them, while the earlier layers' gradients are rounded."""
+    rng = _rng(23)
+    p = cnn.init_params(24).astype(np.float64)
+    x = rng.uniform(0, 1, (5, 6, 4))
+    out, cache = cnn.forward(p, x, bf16=True)
+    n = out.size
+    step = 2.0 ** rng.integers(-6, 0, out.shape) * rng.choice([-1.0, 1.0], out.shape)
+    t = out - step * n / 2.0          # 2 (out - t) / n = step, up to one FP64 rounding
+    g64 = cnn.backward(cache, out, t)
+    g16 = cnn.backward(cache, out, t, bf16=True)
+    assert np.allclose(g16[10432:], g64[10432:], rtol=1e-12, atol=0.0)
+    assert not np.array_equal(g16[:10432], g64[:10432])

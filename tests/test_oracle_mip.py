@@ -208,11 +208,15 @@ def test_bricked_and_full_match_brute_force(kind, step):
     stored = rc.store_bricks(vol, bricks, "f32")
     full = mip.render_mip_full(vol, cam, tf, step)
     br = mip.render_mip_bricked(stored, dims, cam, tf, step)
-    n_hit = 0
+    n_hit = n_tie = 0
     for r in range(v.width * v.height):
         px, py = r % v.width, r // v.width
         m, cnt = _brute_mip_ray(vol, cam, step, px, py)
         if r in br.branches:
+            # a near-tie ray: the brute force takes one of its listed results
+            exp = np.zeros(4) if m is None else mip.colour_map(tf, np.array([m]))[0]
+            assert min(np.max(np.abs(a - exp)) for a in br.branches[r]) < 1e-12
+            n_tie += 1
             continue
         assert full.samples[r] == cnt and br.samples[r] == cnt
         if m is None:
@@ -288,3 +292,31 @@ def test_fp8_bricks_decode_with_their_own_quantisation():
     bound = max(sb.scale for sb in s8) * 32.0
     assert np.max(np.abs(a.vmax[hit] - b.vmax[hit])) <= bound
     assert np.max(np.abs(a.vmax[hit] - b.vmax[hit])) > 0.0
+
+
+def test_sample_on_a_face_between_fp8_bricks_lists_both_maxima():
+    """A sample lands exactly on the face z = 3 between two FP8 bricks with
+    different scale and offset, and it is the largest of the ray.  The ray's
+    results are the colour map of its value decoded from either brick (codes
+    worked out by hand from the E4M3 grid) and nothing else."""
+    dims = (2, 2, 6)
+    zcol = np.array([0.0, 1.0, 3.0, 2.0, 0.5, 0.25], np.float32)
+    vol = np.broadcast_to(zcol[:, None, None], (6, 2, 2)).astype(np.float32)
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (2, 2, 3)), "fp8")
+    a, b = stored
+    assert [float(rc._E4M3_LUT[c]) for c in a.codes[:, 0, 0]] == [-448.0, -448.0, -144.0, 448.0, 144.0]
+    assert [float(rc._E4M3_LUT[c]) for c in b.codes[:, 0, 0]] == [448.0, 120.0, -352.0, -448.0, -448.0]
+    v3a = 0.5 * ((448.0 * a.scale + a.offset) + (144.0 * a.scale + a.offset))
+    v3b = 0.5 * ((120.0 * b.scale + b.offset) + (448.0 * b.scale + b.offset))
+    v5 = 0.5 * ((-352.0 * b.scale + b.offset) + (-448.0 * b.scale + b.offset))
+    assert abs(v3a - v3b) > 1e-3 and v5 < min(v3a, v3b)
+    tf = _identity_map(0.0, 4.0)
+    cam = _cam(synth.axis_view(dims, "z", 2, 2, step=2.0))
+    res = mip.render_mip_bricked(stored, dims, cam, tf, 2.0)
+    assert res.tie.all()
+    for r in range(4):
+        reds = sorted(float(x[0]) for x in res.branches[r])
+        assert len(reds) == 2
+        assert abs(reds[0] - min(v3a, v3b) / 4.0) < 1e-12 and abs(reds[1] - max(v3a, v3b) / 4.0) < 1e-12
+        # the FP64 default: the half-open box puts z = 3 in brick 1
+        assert abs(res.image[r, 0] - v3b / 4.0) < 1e-12

@@ -271,13 +271,17 @@ def test_bricked_matches_brute_force_8cube(kind, brick, tau, frame):
     dt = 0.37
     res = rc.render_bricked(stored, dims, cam, tf, dt, tau)
     k = 0
+    n_tie = 0
     for py in range(16):
         for px in range(20):
-            if res.tie[k]:
-                k += 1
-                continue
             exp = _brute_bricked_ray(vol, bricks, cam, tf, dt, tau, px, py)
-            assert np.allclose(res.image[k], exp, atol=1e-12), (px, py)
+            if res.tie[k]:
+                # the brute force takes one of the ray's enumerated results
+                n_tie += 1
+                assert not res.overflow[k]
+                assert min(np.max(np.abs(a - exp)) for a in res.branches[k]) < 1e-12, (px, py)
+            else:
+                assert np.allclose(res.image[k], exp, atol=1e-12), (px, py)
             k += 1
     assert res.image[:, 3].max() > 0.3
 
@@ -501,3 +505,117 @@ def test_branch_enumeration_consistent_with_vectorised_path():
     for alts in r2.branches.values():
         distinct = {tuple(np.round(a, 14)) for a in alts}
         assert len(distinct) == 2
+
+
+# ----------------------------------------------- near ties with known results
+def _dyadic_tf(rgb, alpha, vmin=0.0, vmax=1.0, dt_ref=1.0):
+    """Two entries over [vmin, vmax]: transparent black, then (rgb, alpha)."""
+    rgba = np.array([[0.0, 0.0, 0.0, 0.0], list(rgb) + [alpha]], np.float32)
+    return rc.TransferFunction(rgba, vmin, vmax, dt_ref)
+
+
+def _alpha_set(results):
+    return sorted({float(r[3]) for r in results})
+
+
+def test_exact_termination_tie_two_bricks_closed_form():
+    """A column of constant density with opacity 1/2 per sample and tau = 3/4:
+    each brick's opacity reaches tau exactly (in binary) at its second sample.
+    A brick may stop there (opacity 3/4) or one sample later (7/8), never
+    elsewhere, so two bricks composite to exactly three distinct pixels,
+    alpha 1 - 2^-4, 1 - 2^-5, 1 - 2^-6, each with colour rgb * alpha."""
+    dims = (1, 1, 8)
+    vol = np.ones(dims[::-1], np.float32)
+    rgb = (0.75, 0.5, 0.25)
+    tf = _dyadic_tf(rgb, 0.5)
+    cam = _cam(synth.axis_view(dims, "z", 1, 1, step=1.0))
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (1, 1, 4)))
+    res = rc.render_bricked(stored, dims, cam, tf, 1.0, 0.75)
+    assert res.tie[0] and not res.overflow[0]
+    assert res.image[0, 3] == 0.9375                       # the FP64 decisions: both bricks stop at 3/4
+    alts = res.branches[0]
+    assert _alpha_set(alts) == [1 - 2.0 ** -4, 1 - 2.0 ** -5, 1 - 2.0 ** -6]
+    assert len(alts) == 3
+    for a in alts:
+        assert np.array_equal(a[:3], np.asarray(rgb) * a[3])
+
+
+def test_termination_tie_over_a_long_transparent_run_is_enumerated_without_cap():
+    """Opacity sits within the tie margin of tau across 148 transparent
+    samples: every stop among them gives the same sub-image, so the ray has
+    as many distinct results as the two-brick closed form (three), and the
+    enumeration does not overflow."""
+    dims = (1, 1, 400)
+    col = np.zeros(400, np.float32)
+    col[0:2] = 1.0
+    col[150:] = 1.0
+    vol = col.reshape(400, 1, 1)
+    tf = _dyadic_tf((0.75, 0.5, 0.25), 0.5)
+    tau = 0.75 + 2.0 ** -15
+    cam = _cam(synth.axis_view(dims, "z", 1, 1, step=1.0))
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (1, 1, 200)))
+    res = rc.render_bricked(stored, dims, cam, tf, 1.0, tau)
+    assert res.tie[0] and not res.overflow[0]
+    # FP64: brick 0 never reaches tau before sample 150 (opacity 7/8), brick 1 at its third sample
+    assert res.image[0, 3] == 0.875 + 0.125 * 0.875
+    alts, ovf = rc.ray_branches(stored, dims, cam, tf, 1.0, tau, 0, 0)
+    assert not ovf
+    assert _alpha_set(alts) == [1 - 2.0 ** -4, 1 - 2.0 ** -5, 1 - 2.0 ** -6]
+
+
+def test_sample_on_a_face_between_fp8_bricks_closed_form():
+    """A sample lands exactly on the face z = 3 between two FP8 bricks with
+    different scale and offset.  It belongs to either brick; its value is the
+    mean of voxels 2 and 3 decoded with that brick's codes, scale and offset
+    (codes worked out by hand from the E4M3 grid).  The ray has exactly the
+    two results composited from those values."""
+    dims = (2, 2, 6)
+    zcol = np.array([0.0, 1.0, 3.0, 2.0, 0.5, 0.25], np.float32)
+    vol = np.broadcast_to(zcol[:, None, None], (6, 2, 2)).astype(np.float32)
+    bricks = rc.brick_grid(dims, (2, 2, 3))
+    stored = rc.store_bricks(vol, bricks, "fp8")
+    a, b = stored
+    # brick 0 stores z = 0, 0, 1, 2, 3 (ghost below clamps): min 0, max 3;
+    # brick 1 stores z = 2, 3, 4, 5, 5: min 0.25, max 3
+    assert a.offset == 1.5 and a.scale == float(np.float32(np.float32(3.0) / np.float32(896.0)))
+    assert b.offset == 1.625 and b.scale == float(np.float32(np.float32(2.75) / np.float32(896.0)))
+    # codes: (v - o) / s on the E4M3 grid (binades [64, 128), [128, 256), [256, 448] have steps 8, 16, 32)
+    assert [float(rc._E4M3_LUT[c]) for c in a.codes[:, 0, 0]] == [-448.0, -448.0, -144.0, 448.0, 144.0]
+    assert [float(rc._E4M3_LUT[c]) for c in b.codes[:, 0, 0]] == [448.0, 120.0, -352.0, -448.0, -448.0]
+    dec_a = lambda q: q * a.scale + a.offset
+    dec_b = lambda q: q * b.scale + b.offset
+    v1 = 0.5 * (dec_a(-448.0) + dec_a(-144.0))          # sample z = 1, brick 0
+    v3 = {"a": 0.5 * (dec_a(448.0) + dec_a(144.0)),      # sample z = 3 in brick 0 (voxel 3 = its ghost)
+          "b": 0.5 * (dec_b(120.0) + dec_b(448.0))}      # ... in brick 1 (voxel 2 = its ghost)
+    v5 = 0.5 * (dec_b(-352.0) + dec_b(-448.0))           # sample z = 5, brick 1
+    assert abs(v3["a"] - v3["b"]) > 1e-3
+    rgb = np.array([1.0, 0.5, 0.25])
+    tf = _dyadic_tf(rgb, 0.75, vmin=0.0, vmax=4.0, dt_ref=2.0)
+    expected = []
+    for k in ("a", "b"):
+        al = [0.75 * v / 4.0 for v in (v1, v3[k], v5)]
+        A = al[0] + (1 - al[0]) * al[1] + (1 - al[0]) * (1 - al[1]) * al[2]
+        expected.append(np.concatenate([rgb * A, [A]]))
+    cam = _cam(synth.axis_view(dims, "z", 2, 2, step=2.0))
+    res = rc.render_bricked(stored, dims, cam, tf, 2.0, 1.0)
+    assert res.tie.all() and not res.overflow.any()
+    for r in range(4):
+        alts = res.branches[r]
+        assert len(alts) == 2
+        for e in expected:
+            assert min(np.max(np.abs(x - e)) for x in alts) < 1e-12
+        # the FP64 default: the half-open box puts z = 3 in brick 1
+        assert np.max(np.abs(res.image[r] - expected[1])) < 1e-12
+
+
+def test_psnr_peak_one_decibels_base_ten():
+    """PSNR = 10 log10(1 / MSE) with peak 1 over every pixel and channel."""
+    a = np.zeros((10, 10, 4))
+    b = a.copy()
+    b[3, 4, 2] = 0.4                                      # MSE = 0.16 / 400 = 4e-4
+    assert abs(rc.psnr(a, b) - (40.0 - 10.0 * math.log10(4.0))) < 1e-9
+    b[:] = 0.01                                           # MSE = 1e-4 -> 40 dB
+    assert abs(rc.psnr(a, b) - 40.0) < 1e-9
+    assert abs(rc.psnr(np.zeros(8), np.full(8, 0.5)) - 10.0 * math.log10(4.0)) < 1e-12   # 6.02 dB
+    assert rc.psnr(np.zeros(8), np.ones(8)) == 0.0
+    assert rc.psnr(b, b) == math.inf
