@@ -19,6 +19,15 @@ sub-image tiles written (1 KiB per 8x8 tile).  ``cpu_baseline`` is the FP64
 oracle timed on a bounded random sample of the first frame's pixels, in
 processes forked over the host cores before the GPU is touched.
 
+On the default workload the line also carries ``forms``: the same orbit
+rendered from FP16 and FP8-E4M3 bricks (each from its own context, loaded
+from the same cube) and as learned frames (half-size coarse render plus the
+trained upsampler, validated against plain tiles at 40 dB), each with its
+milliseconds per frame, its speedup over plain FP32, its PSNR against the
+plain FP32 frames and (storage forms) against the FP64 oracle on the FP32
+cube, and whether it counts as chosen (PSNR >= 40 dB against plain on every
+frame compared).
+
 ``--op mip`` runs the same path with maximum intensity projection (the
 paper's operator: per-ray maximum, any-order merge, colour map after the
 merge), with ``--step-policy voxel`` at one sample per voxel slice per ray.
@@ -115,7 +124,10 @@ def parse():
     p.add_argument("--workload", choices=sorted(WORKLOADS), default="cube1024_persp1920x1080")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target wall time of the oracle sample (0 disables the CPU baseline)")
-    p.add_argument("--cpu-workers", type=int, default=0, help="0 = all host cores, at most 16")
+    p.add_argument("--cpu-workers", type=int, default=0,
+                   help="0 = every core this process may use (affinity mask, capped by the cgroup CPU quota)")
+    p.add_argument("--forms", type=int, choices=(0, 1), default=1,
+                   help="1: also time FP16, FP8 and learned frames on the default workload (plain FP32 only)")
     p.add_argument("--op", choices=("composite", "mip"), default="composite",
                    help="ray operator: front-to-back compositing, or maximum intensity projection")
     p.add_argument("--step-policy", choices=("fixed", "voxel"), default="fixed",
@@ -137,15 +149,28 @@ def parse():
     return p.parse_args()
 
 
-def views_for(recipe, width, height):
-    kind = "persp" if width != height else "ortho"
+def host_cores() -> int:
+    """Cores this process may run on: the affinity mask, capped by the cgroup
+    CPU quota when one is set (a container's share of a larger host)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            quota, period = fh.read().split()[:2]
+        if quota != "max":
+            n = min(n, max(1, int(float(quota) / float(period))))
+    except (OSError, ValueError):
+        pass
+    return max(1, n)
+
+
+def views_for(recipe, width, height, kind):
     return [synth.orbit_view(recipe.dims, k, ORBIT, kind=kind, width=width, height=height, step=0.5, ert=0.99)
             for k in range(ORBIT)]
 
 
-def view_sets(recipe, width, height, per_launch, n):
+def view_sets(recipe, width, height, per_launch, n, kind):
     """Launch i renders orbit frames i, i + 64/v, ... (v views per launch)."""
-    orbit = views_for(recipe, width, height)
+    orbit = views_for(recipe, width, height, kind)
     stride = ORBIT // per_launch
     n_sets = max(1, min(stride, n))
     return [[orbit[i + j * stride] for j in range(per_launch)] for i in range(n_sets)]
@@ -288,6 +313,94 @@ def setup_learned(bc, args, views, out, W, H):
     return summary
 
 
+# ------------------------------------------------------------------ other forms
+def timed_frames(bc, sets, out, steps, warmup):
+    """Wall-clock ms per frame over `steps` frames after `warmup` (inputs
+    resident), with the summed per-stage ms of the timed frames."""
+    import torch
+    nf = len(sets)
+    for i in range(warmup):
+        bc.set_views(sets[i % nf])
+        bc.render(out)
+    torch.cuda.synchronize()
+    bc.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        bc.set_views(sets[i % nf])
+        bc.render(out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_ms, n = bc.timing()
+    bc.enable_timing(False)
+    return elapsed / steps * 1e3, [m / n for m in stage_ms]
+
+
+def psnr_db(a, b) -> float:
+    """PSNR (peak 1) of two device images over every pixel and channel."""
+    mse = float(((a.double() - b.double()) ** 2).mean())
+    return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+def storage_leg(storage, args, recipe, brick, W, H, sets, vol, rgba, vmin, vmax, ref, plain_imgs, base_ms):
+    """The orbit rendered from `storage` bricks in a context of its own: ms per
+    frame, speedup over plain FP32, PSNR against the plain FP32 frames and
+    against the FP64 oracle on the FP32 cube."""
+    import torch
+    from paper_1205_0282_amd import binding
+    dev = torch.device("cuda", 0)
+    bc = binding.BrickCaster(0)
+    bc.plan(recipe.dims, (brick,) * 3, storage=storage, src_dtype="f32", max_views=1, max_w=W, max_h=H)
+    bc.bind()
+    src = torch.from_numpy(vol).to(dev)
+    bc.load(src)
+    torch.cuda.synchronize()
+    del src
+    bc.set_transfer_function(rgba, vmin, vmax)
+    out = torch.empty((1, H, W, 4), dtype=torch.float32, device=dev)
+    samples = []
+    for vs in sets:
+        bc.set_views(vs)
+        bc.render(out)
+        samples.append(bc.stats()["nominal_samples"])
+    ms, stage = timed_frames(bc, sets, out, args.steps, args.warmup)
+    nf = len(sets)
+    gsps = sum(samples[i % nf] for i in range(args.steps)) / args.steps / (ms * 1e-3) / 1e9
+    vs_plain = []
+    for i, img in plain_imgs:
+        bc.set_views(sets[i])
+        vs_plain.append(psnr_db(bc.render(out), img))
+    leg = {"ms_per_frame": ms, "render_ms": stage[1], "gsamples_per_s": gsps, "speedup_vs_f32": base_ms / ms,
+           "psnr_vs_plain_f32_db": {"min": min(vs_plain), "mean": float(np.mean(vs_plain)),
+                                    "frames": len(vs_plain)}}
+    if ref is not None:
+        pix, ref_img, branches = ref
+        bc.set_views(sets[0])
+        img = bc.render(out)[0].cpu().numpy().astype(np.float64)
+        leg["vs_fp64_oracle_on_f32_cube"] = precision_report(img[pix[:, 1], pix[:, 0]], ref_img, branches)
+    leg["chosen"] = bool(leg["psnr_vs_plain_f32_db"]["min"] >= 40.0)
+    bc.close()
+    log(f"{storage}: {leg}")
+    return leg
+
+
+def learned_leg(bc, args, sets, views, out, W, H, base_ms):
+    """Learned frames on the FP32 context: the trained upsampler's quality on
+    every orbit frame (untimed), then the timed orbit at the 40 dB gate."""
+    quality = setup_learned(bc, args, views, out, W, H)
+    ms, _ = timed_frames(bc, sets, out, args.steps, args.warmup)
+    bc.set_learned(False)
+    net = quality["psnr_network_vs_plain_db"]
+    leg = {"ms_per_frame": ms, "speedup_vs_f32": base_ms / ms,
+           "psnr_vs_plain_f32_db": net, "bilinear_psnr_vs_plain_f32_db": quality["psnr_bilinear_vs_plain_db"],
+           "gain_over_bilinear_db": net["mean"] - quality["psnr_bilinear_vs_plain_db"]["mean"],
+           "fell_back_frames": quality["fell_back_frames"], "frames": quality["frames"],
+           "psnr_threshold_db": args.psnr_threshold, "chosen": bool(net["min"] >= 40.0),
+           "weights": quality["weights"]}
+    log(f"learned: {leg}")
+    return leg
+
+
 # ------------------------------------------------------------------ GPU
 def main():
     args = parse()
@@ -305,6 +418,8 @@ def main():
         args.learned, args.check_pixels, args.cpu_seconds = False, 0, 0
     if src_dtype == "f16" and args.storage == "f32":
         args.storage = "f16"
+    forms = (args.forms and args.workload == "cube1024_persp1920x1080" and args.storage == "f32"
+             and args.op == "composite" and not args.learned and not args.graph)
     t = time.perf_counter()
     vol = synth.make_cube(recipe, workers=min(16, os.cpu_count() or 1),
                           out_dtype=np.float16 if src_dtype == "f16" else np.float32)
@@ -319,11 +434,12 @@ def main():
         vmin, vmax = float(vol.min()), float(vol.max())
     log(f"cube {recipe.dims} generated in {time.perf_counter() - t:.1f} s; range [{vmin:.3f}, {vmax:.3f}]")
     rgba = synth.ramp_tf(vmin, vmax)
-    sets = view_sets(recipe, W, H, per_launch, args.frames)
+    # the small parity workload is orthographic, every other one perspective
+    sets = view_sets(recipe, W, H, per_launch, args.frames, "ortho" if "_ortho" in args.workload else "persp")
     views = [vs[0] for vs in sets]
     nf = len(sets)
 
-    workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+    workers = args.cpu_workers or host_cores()
     ref = None
     if args.check_pixels > 0:
         t = time.perf_counter()
@@ -349,7 +465,8 @@ def main():
     bc.load(src)
     torch.cuda.synchronize()
     del src
-    del vol
+    if not forms:
+        del vol
     torch.cuda.empty_cache()
     log(f"bricks loaded in {time.perf_counter() - t:.1f} s")
     bc.set_transfer_function(rgba, vmin, vmax)
@@ -435,6 +552,26 @@ def main():
         paper_stat = {"median_of": args.repeats, "p75_over_angles_ms": float(np.percentile(med, 75)),
                       "mean_ms": float(ft.mean()), "angles": nf}
 
+    ms_step = elapsed / args.steps * 1e3
+    form_legs = None
+    if forms:
+        form_legs = {"f32": {"ms_per_frame": ms_step, "speedup_vs_f32": 1.0}}
+        if os.path.exists(args.weights):
+            form_legs["learned"] = learned_leg(bc, args, sets, views, out, W, H, ms_step)
+        # plain FP32 frames the other forms are compared with
+        picks = list(range(0, nf, max(1, nf // 8)))[:8]
+        plain_imgs = []
+        for i in picks:
+            bc.set_views(sets[i])
+            plain_imgs.append((i, bc.render(out).clone()))
+        bc.close()
+        torch.cuda.empty_cache()
+        for st in ("f16", "fp8"):
+            form_legs[st] = storage_leg(st, args, recipe, brick, W, H, sets, vol, rgba, vmin, vmax, ref,
+                                        plain_imgs, ms_step)
+            torch.cuda.empty_cache()
+        del plain_imgs, vol
+
     idx = [i % nf for i in range(args.steps)]
     tot_samples = float(sum(samples[i] for i in idx))
     tot_bytes = float(sum(algo_bytes[i] for i in idx))
@@ -442,10 +579,11 @@ def main():
         stage_ms = [m * n_timed for m in stage_ms_eager]
     render_s = stage_ms[1] / 1e3
     achieved = tot_bytes / render_s / 1e9
-    ms_step = elapsed / args.steps * 1e3
+    traffic = measured_traffic(f"{args.workload}/{args.storage}/{args.op}/{args.step_policy}")
     result = {
         "metric": (f"Gsamples/s + fps @{W}x{H} on "
-                   + ("1024^3 cube" if recipe.dims == (1024, 1024, 1024) else "x".join(map(str, recipe.dims)) + " cube"))
+                   + ("1024^3 cube" if recipe.dims == (1024, 1024, 1024) else "x".join(map(str, recipe.dims)) + " cube")
+                   + ("; learned/FP8 vs plain at PSNR>=40dB" if forms else ""))
                   if per_launch == 1 else
                   f"Gsamples/s + launches/s @{W}x{H}, {per_launch} views per launch, "
                   + "x".join(map(str, recipe.dims)) + " FP16 cube",
@@ -477,14 +615,19 @@ def main():
         "roofline": None if args.learned else {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(f"{args.workload}/{args.storage}/{args.op}/{args.step_policy}"),
-            "kernel": "render_kernel", "algo_bytes_per_launch": tot_bytes / args.steps},
+            "traffic": traffic,
+            "kernel": "render_kernel", "algo_bytes_per_launch": tot_bytes / args.steps,
+            # HBM bytes actually moved (counters), as a bandwidth and a fraction of peak
+            "traffic_gbs": None if traffic is None else traffic / (render_s / args.steps) / 1e9,
+            "traffic_frac": None if traffic is None else traffic / (render_s / args.steps) / 1e9 / HBM_PEAK_GBS},
         "paper_statistic": paper_stat,
         "precision_vs_oracle": precision,
         "learned": learned,
+        "forms": form_legs,
         "cpu_baseline": cpu,
     }
-    bc.close()
+    if not forms:
+        bc.close()
     print(json.dumps(result), flush=True)
 
 

@@ -84,7 +84,7 @@ typedef struct {
 
 /* Sizes (bytes) of the four device regions for a volume and the largest frame
  * to be rendered:
- *   bytes_out[0] brick pool     (bricks with ghosts, Z-order micro-blocks)
+ *   bytes_out[0] brick pool     (bricks with ghosts, as 4x4x4 micro-blocks; see bc_read_brick)
  *   bytes_out[1] metadata       (brick table, views, order, rectangles, queue, counters, table,
  *                                one occupancy bit per interpolation cell of every brick)
  *   bytes_out[2] sub-images     (max_tiles sub-image tiles of 8x8 RGBA float32)

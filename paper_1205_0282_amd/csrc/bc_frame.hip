@@ -449,15 +449,19 @@ __global__ __launch_bounds__(1024) void composite_kernel(BcFramePtrs f, float4* 
 // render over the validation tiles, and the fall-back decision.
 __global__ __launch_bounds__(1024) void psnr_kernel(BcFramePtrs f, const float4* __restrict__ ref,
                                                     const float4* __restrict__ img) {
-  __shared__ double red[1024];
+  // FP32 throughout: each thread keeps a compensated (Kahan) sum of its
+  // pixels' squared differences, and the block adds the 1024 partial sums
+  // pairwise (relative error about 10 roundings)
+  __shared__ float red[1024];
+  __shared__ int nred[1024];
   const int ts = f.fin->tile_stride, tox = f.fin->tile_ox, toy = f.fin->tile_oy;
   const int W = f.width, H = f.height, nv = f.n_views;
   const int tiles_x = (W + BC_TILE - 1) / BC_TILE, tiles_y = (H + BC_TILE - 1) / BC_TILE;
   const int sx = sel_count(0, tiles_x, ts, tox), sy = sel_count(0, tiles_y, ts, toy);
   const int fx = sel_first(0, ts, tox), fy = sel_first(0, ts, toy);
   const int64_t total = (int64_t)nv * sx * sy * 64;
-  double acc = 0.0;
-  double cnt = 0.0;
+  float acc = 0.0f, comp = 0.0f;
+  int cnt = 0;
   for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
     const int lane = (int)(e & 63);
     const int64_t t = e >> 6;
@@ -468,27 +472,27 @@ __global__ __launch_bounds__(1024) void psnr_kernel(BcFramePtrs f, const float4*
     if (px >= W || py >= H) continue;
     const int64_t i = ((int64_t)v * H + py) * W + px;
     const float4 a = ref[i], b = img[i];
-    const double dx = (double)a.x - b.x, dy = (double)a.y - b.y, dz = (double)a.z - b.z, dw = (double)a.w - b.w;
-    acc += dx * dx + dy * dy + dz * dz + dw * dw;
-    cnt += 4.0;
+    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
+    const float term = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, dw * dw)));
+    const float y = term - comp;
+    const float t2 = acc + y;
+    comp = (t2 - acc) - y;
+    acc = t2;
+    cnt += 4;
   }
   red[threadIdx.x] = acc;
+  nred[threadIdx.x] = cnt;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double sum = red[0];
-  __syncthreads();
-  red[threadIdx.x] = cnt;
-  __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) {
+      red[threadIdx.x] += red[threadIdx.x + s];
+      nred[threadIdx.x] += nred[threadIdx.x + s];
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double mse = red[0] > 0.0 ? sum / red[0] : 0.0;
-    const float p = mse > 0.0 ? (float)(10.0 * log10(1.0 / mse)) : INFINITY;
+    const float mse = nred[0] > 0 ? red[0] / (float)nred[0] : 0.0f;
+    const float p = mse > 0.0f ? 10.0f * log10f(1.0f / mse) : INFINITY;
     f.ctr->psnr_db = p;
     f.ctr->fallback = (p < f.fin->psnr_threshold) ? 1u : 0u;
   }

@@ -188,13 +188,21 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs a) {
     const int vmax_x = ncx, vmax_y = ncy, vmax_z = ncz;   // last ghosted voxel index
     float v[3][5][5];
     const float s_q = br.scale, o_q = br.offs;
+    // FP8 compositing: the ray caster interpolates the codes' values and maps
+    // the result to the table with the brick's scale and offset folded in,
+    // fma(q, scale * s, fma(o, scale, bias)); the cells are bounded through
+    // the same mapping of the same values, so that every index the ray caster
+    // can form lies inside the checked range
+    const bool fold = FMT == 2 && !a.mip;
+    const float csc = fold ? sc * s_q : sc, cbi = fold ? __builtin_fmaf(o_q, sc, bi) : bi;
+    const float ds = fold ? 1.0f : s_q, dof = fold ? 0.0f : o_q;
     const void* pool = static_cast<const char*>(a.pool) + br.offset * (FMT == 0 ? 4 : (FMT == 1 ? 2 : 1));
     for (int z = 0; z < 3; ++z)
       for (int y = 0; y < 5; ++y)
         for (int x = 0; x < 5; ++x) {
           const int gx = clampi(wx * 4 + x, 0, vmax_x), gy = clampi(wy * 4 + y, 0, vmax_y),
                     gz = clampi(wz * 2 + z, 0, vmax_z);
-          v[z][y][x] = fetch<FMT>(pool, vox_index(gx, gy, gz, br.mb[0], br.mb[1]), s_q, o_q);
+          v[z][y][x] = fetch<FMT>(pool, vox_index(gx, gy, gz, br.mb[0], br.mb[1]), ds, dof);
         }
     uint32_t bits = 0;
     for (int cz = 0; cz < 2; ++cz)
@@ -209,7 +217,7 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs a) {
           }
           // trilinear values lie within the corner range up to a few roundings
           const float m = fmaxf(fabsf(lo), fabsf(hi)) * 9.5367431640625e-07f + 1e-30f;   // 2^-20
-          float xl = __builtin_fmaf(lo - m, sc, bi), xh = __builtin_fmaf(hi + m, sc, bi);
+          float xl = __builtin_fmaf(lo - m, csc, cbi), xh = __builtin_fmaf(hi + m, csc, cbi);
           xl = fminf(fmaxf(xl, 0.0f), kmax);
           xh = fminf(fmaxf(xh, 0.0f), kmax);
           const int il = a.mip ? 0 : min((int)xl, K - 2), ih = min((int)xh, K - 2) + 1;

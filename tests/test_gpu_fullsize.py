@@ -1,10 +1,18 @@
 """Parity at the benchmark's full size: the 1024^3 FP32 cube (4x4x4 bricks of
 256^3), perspective 1920x1080, rendered by the same launch configuration
 bench.py times, against the FP64 oracle at sampled pixels (each computed one
-by one by the oracle): compositing with step 0.5 and termination at 0.99, and
-maximum intensity projection with the per-voxel step; and the same cube stored
-FP16 and FP8 (the precision workload) against the oracle on the stored
-values."""
+by one by the oracle): compositing with step 0.5 and termination at 0.99
+(uniformly drawn pixels of two frames, and every pixel of a 48x48 block), and
+maximum intensity projection with the per-voxel step; the paper's output
+sizes 1024x1024 and 2048x2048 (its frame-size experiment, Section 3.2) on the
+same cube; the same cube stored FP16 and FP8 (the precision workload) against
+the oracle on the stored values; and what the trained upsampler gains over
+bilinear upsampling of the same coarse render on this cube, which it was not
+trained on."""
+import math
+import multiprocessing as mp
+import os
+
 import numpy as np
 import pytest
 
@@ -26,7 +34,7 @@ def cube1024():
     rgba = synth.ramp_tf(vmin, vmax)
     dims = recipe.dims
     bc = binding.BrickCaster(0)
-    bc.plan(dims, (256, 256, 256), storage="f32", max_views=1, max_w=1920, max_h=1080)
+    bc.plan(dims, (256, 256, 256), storage="f32", max_views=1, max_w=2048, max_h=2048)
     bc.bind()
     src = torch.from_numpy(vol).cuda()
     bc.load(src)
@@ -38,12 +46,40 @@ def cube1024():
     bc.close()
 
 
-def _pixels(cam, dims, seed):
+def _pixels(cam, dims, seed, W=1920, H=1080, n_hit=96):
     rng = np.random.default_rng(seed)
-    cand = np.stack([rng.integers(0, 1920, 2000), rng.integers(0, 1080, 2000)], axis=1)
+    cand = np.stack([rng.integers(0, W, 20 * n_hit), rng.integers(0, H, 20 * n_hit)], axis=1)
     o, d = cam.rays(cand[:, 0], cand[:, 1])
     _, _, hit = rc.global_interval(o, d, dims)
-    return np.concatenate([cand[hit][:96], cand[~hit][:16]])
+    return np.concatenate([cand[hit][:n_hit], cand[~hit][:16]])
+
+
+_POOL_ARGS = {}
+
+
+def _oracle_chunk(pix):
+    a = _POOL_ARGS
+    return rc.render_bricked(a["stored"], a["dims"], a["cam"], a["tf"], 0.5, 0.99, pixels=pix)
+
+
+def _oracle_pixels(stored, dims, cam, tf, pix, workers):
+    """The bricked oracle at many pixels, over forked worker processes (numpy
+    only: the workers never call the GPU), merged into one result."""
+    _POOL_ARGS.update(stored=stored, dims=dims, cam=cam, tf=tf)
+    chunks = [c for c in np.array_split(pix, workers * 4) if len(c)]
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_oracle_chunk, chunks)
+    finally:
+        _POOL_ARGS.clear()
+    branches, base = {}, 0
+    for r in parts:
+        branches.update({base + k: v for k, v in r.branches.items()})
+        base += len(r.image)
+    return rc.RenderResult(image=np.concatenate([r.image for r in parts]),
+                           tie=np.concatenate([r.tie for r in parts]), branches=branches,
+                           overflow=np.concatenate([r.overflow for r in parts]),
+                           samples=np.concatenate([r.samples for r in parts]))
 
 
 def test_cube1024_frame_sampled_pixels(cube1024):
@@ -59,6 +95,101 @@ def test_cube1024_frame_sampled_pixels(cube1024):
         err, _, _ = compare(img[pix[:, 1], pix[:, 0]], res, f"frame {frame}")
         assert err <= TOL
         assert res.image[:, 3].max() > 0.1
+
+
+def test_cube1024_frame_dense_block(cube1024):
+    """Every pixel of a 48x48 block of orbit frame 0 that straddles the edge
+    of the cube's silhouette and crosses brick faces."""
+    bc, stored, tf, dims = cube1024["bc"], cube1024["stored"], cube1024["tf"], cube1024["dims"]
+    bc.set_operator("composite", "fixed")
+    v = synth.orbit_view(dims, 0)
+    bc.set_views([v])
+    img = bc.render()[0].cpu().numpy().astype(np.float64)
+    cam = cam_of(v)
+    # the block around the point where the silhouette's left edge crosses the
+    # middle row, and around the centre column
+    row = 540
+    o, d = cam.rays(np.arange(1920), np.full(1920, row))
+    _, _, hit = rc.global_interval(o, d, dims)
+    x_edge = int(np.argmax(hit))
+    blocks = [(max(x_edge - 24, 0), row - 24), (960 - 24, 540 - 24)]
+    pix = np.concatenate([np.stack(np.meshgrid(np.arange(x0, x0 + 48), np.arange(y0, y0 + 48)), -1).reshape(-1, 2)
+                          for x0, y0 in blocks])
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    res = _oracle_pixels(stored, dims, cam, tf, pix, workers)
+    err, _, _ = compare(img[pix[:, 1], pix[:, 0]], res, f"frame 0, {len(pix)} pixels of two 48x48 blocks")
+    assert err <= TOL
+    o, d = cam.rays(pix[:, 0], pix[:, 1])
+    _, _, hit = rc.global_interval(o, d, dims)
+    assert 0 < hit[:2304].sum() < 2304 and hit[2304:].all()   # the first block straddles the silhouette
+
+
+@pytest.mark.parametrize("size", [1024, 2048])
+def test_cube1024_paper_output_sizes(cube1024, size):
+    """The paper's frame sizes (1024x1024 in its node-scaling runs, 2048x2048
+    in its frame-size experiment, Section 3.2): perspective orbit frames of
+    the bench cube in the launch configuration bench.py times."""
+    bc, stored, tf, dims = cube1024["bc"], cube1024["stored"], cube1024["tf"], cube1024["dims"]
+    bc.set_operator("composite", "fixed")
+    v = synth.orbit_view(dims, 9, kind="persp", width=size, height=size)
+    bc.set_views([v])
+    img = bc.render()[0].cpu().numpy().astype(np.float64)
+    cam = cam_of(v)
+    pix = _pixels(cam, dims, 300 + size, size, size, 128)
+    res = rc.render_bricked(stored, dims, cam, tf, 0.5, 0.99, pixels=pix)
+    err, _, _ = compare(img[pix[:, 1], pix[:, 0]], res, f"{size}x{size}")
+    assert err <= TOL
+    assert res.image[:, 3].max() > 0.1
+    st = bc.stats()
+    print(f"{size}x{size}: {st['nominal_samples'] / 1e6:.1f} M samples, {st['n_tiles']} tiles", flush=True)
+
+
+def test_trained_upsampler_gains_over_bilinear(cube1024):
+    """The shipped upsampler on the bench cube (seed 2; the network was
+    trained on other seeds): on orbit frames its PSNR against the plain
+    1920x1080 render beats bilinear upsampling of the same 960x540, step-2
+    render by at least 0.5 dB on every frame; and a learned frame at the 40 dB
+    gate falls back exactly when its validation PSNR is below 40 dB."""
+    import torch
+    import torch.nn.functional as F
+    bc, dims = cube1024["bc"], cube1024["dims"]
+    bc.set_operator("composite", "fixed")
+    w = np.load(os.path.join(os.path.dirname(binding.__file__), "weights", "upsampler.npy"), allow_pickle=False)
+    bc.cnn_setup(1, 540, 960)
+    bc.cnn_set_weights(w.astype(np.float32))
+
+    def psnr(a, b):
+        mse = float(((a.double() - b.double()) ** 2).mean())
+        return 10 * math.log10(1.0 / mse)
+
+    gains, passed = [], 0
+    try:
+        for frame in (0, 13, 29, 46):
+            v = synth.orbit_view(dims, frame)
+            bc.set_learned(False)
+            bc.set_views([v])
+            plain = bc.render().clone()
+            bc.set_views([synth.orbit_view(dims, frame, width=960, height=540, step=2.0)])
+            coarse = bc.render().clone()
+            net = bc.cnn_forward(coarse)
+            bil = F.interpolate(coarse.permute(0, 3, 1, 2), scale_factor=2, mode="bilinear",
+                                align_corners=False).permute(0, 2, 3, 1)
+            p_net, p_bil = psnr(net, plain), psnr(bil, plain)
+            gains.append(p_net - p_bil)
+            bc.set_views([v])
+            bc.set_learned(True, 2.0, 40.0, 8)
+            learned = bc.render().clone()
+            st = bc.stats()
+            assert st["fell_back"] == (1 if st["psnr_db"] < 40.0 else 0)
+            # the frame is the network's output, or the plain frame after a fall-back
+            assert torch.equal(learned, plain if st["fell_back"] else net)
+            passed += st["fell_back"] == 0
+            print(f"frame {frame}: network {p_net:.2f} dB, bilinear {p_bil:.2f} dB, gain {p_net - p_bil:.2f} dB, "
+                  f"validation {st['psnr_db']:.2f} dB, fell back {st['fell_back']}", flush=True)
+    finally:
+        bc.set_learned(False)
+    print(f"{passed} of {len(gains)} frames passed the 40 dB gate", flush=True)
+    assert min(gains) >= 0.5
 
 
 def test_cube1024_mip_per_voxel_sampled_pixels(cube1024):
