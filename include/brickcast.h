@@ -150,6 +150,25 @@ int bc_set_view(bc_ctx* ctx, const bc_view* views, int n_views);
  * missing; BC_E_ARG for a null or misaligned out. */
 int bc_render_frame(bc_ctx* ctx, float* out, void* stream);
 
+/* The same frame as bc_render_frame, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the sub-image tiles go to a fixed device array that the library
+ * holds on each device it runs on (BC_STATIC_MAX_TILES tiles of 8x8 RGBA
+ * float32, 64 MiB, kept until the process ends) instead of the bound
+ * sub-image region, and the call allocates nothing, host or device: it
+ * launches the kernels directly (it ignores BC_OPT_GRAPH, whose capture and
+ * instantiation allocate) and is not counted in the bc_enable_timing window
+ * (timing creates its events on demand).  Images are those of
+ * bc_render_frame.  Calls on one GPU share its array and each overwrites what
+ * the last left there: frames enqueued on different streams that may overlap
+ * on one GPU race and give wrong images; frames on one stream, or on streams
+ * that are ordered, are safe.  Errors: as bc_render_frame; BC_E_NOMEM (before
+ * anything is enqueued) if the current views need more than
+ * BC_STATIC_MAX_TILES sub-image tiles (the bound that bc_set_view checks
+ * against the plan, here checked against the array). */
+#define BC_STATIC_MAX_TILES 65536
+int bc_render_frame_static(bc_ctx* ctx, float* out, void* stream);
+
 /* Learned frames (enable = 1; needs the upsampler workspace and weights, see
  * bc_cnn_* below, and an even frame width and height).  A learned frame
  * renders the views at half the width and height with step `coarse_step`

@@ -26,8 +26,9 @@ EXPORTS = [
     "bc_enable_timing", "bc_get_timing", "bc_set_option",
     "bc_cnn_plan", "bc_cnn_bind", "bc_cnn_set_weights", "bc_cnn_get_weights", "bc_cnn_forward",
     "bc_cnn_gradients", "bc_cnn_train_step", "bc_set_learned", "bc_autotune", "bc_get_frame_times",
-    "bc_set_operator",
+    "bc_set_operator", "bc_render_frame_static",
 ]
+BC_STATIC_MAX_TILES = 65536
 CNN_N_PARAMS = 15056
 BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS, BC_OPT_SAMPLE_CHUNK, BC_OPT_GRAPH, BC_OPT_XCD_QUEUES = 0, 1, 2, 3, 4
 BC_OP_COMPOSITE, BC_OP_MIP = 0, 1
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "bc_set_transfer_function": (I, [P, C.POINTER(F), I, D, D, D]),
         "bc_set_view": (I, [P, C.POINTER(View), I]),
         "bc_render_frame": (I, [P, P, P]),
+        "bc_render_frame_static": (I, [P, P, P]),
         "bc_get_frame_stats": (I, [P, C.POINTER(FrameStats)]),
         "bc_get_bricks": (I, [P, C.POINTER(C.c_int32), C.POINTER(F), C.POINTER(F), I, C.POINTER(I)]),
         "bc_get_visibility_order": (I, [P, I, C.POINTER(C.c_int32), I]),
@@ -222,6 +224,17 @@ class BrickCaster:
                               device=torch.device("cuda", self.device))
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         self._check(self.lib.bc_render_frame(self.h, C.c_void_p(out.data_ptr()), C.c_void_p(st)))
+        return out
+
+    def render_static(self, out=None, stream=None):
+        """bc_render_frame_static: the same frame with the sub-image tiles in
+        the library's fixed device array (no allocation by the library)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_views, self.height, self.width, 4), dtype=torch.float32,
+                              device=torch.device("cuda", self.device))
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self.lib.bc_render_frame_static(self.h, C.c_void_p(out.data_ptr()), C.c_void_p(st)))
         return out
 
     # ------------------------------------------------------------- queries

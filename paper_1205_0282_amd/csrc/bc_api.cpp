@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,19 +19,47 @@
 #include "bc_kernels.h"
 #include "bc_types.h"
 
+// Sub-image tiles of bc_render_frame_static: a fixed device array in place of
+// the bound sub-image region, for callers that cannot allocate.  Each device
+// the library runs on holds its own copy until the process ends.  In host code
+// the name is only a stand-in: kernels are given the device address that
+// hipGetSymbolAddress returns for it (kept per device below), never the name.
+static __device__ __align__(256) float4 scratch[(size_t)BC_STATIC_MAX_TILES * BC_TILE * BC_TILE];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+// device address of `scratch` on each device, looked up once per device
+std::mutex g_scratch_mu;
+std::map<int, float4*> g_scratch_ptr;
+
+// looks up the address of `scratch` on `device` (which must be current) the
+// first time, then returns the kept one; nullptr on failure
+float4* static_scratch(int device, hipError_t* err) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    if (err) *err = e;
+    return nullptr;
+  }
+  g_scratch_ptr[device] = static_cast<float4*>(ptr);
+  return static_cast<float4*>(ptr);
+}
 
 struct GraphKey {
   bool learned = false, ess = false, xcd = false;
   int n_views = 0, W = 0, H = 0, K = 0, chunk = 0, wgs = 0, op = 0, step_policy = 0;
   int64_t split = 0;   // learned frames: sub-image tiles set aside for the concurrent validation pass (0: serial)
   const void* out = nullptr;
+  const void* sub = nullptr;   // sub-image tiles the launches write
   bool operator==(const GraphKey& o) const {
     return learned == o.learned && ess == o.ess && xcd == o.xcd && n_views == o.n_views && W == o.W && H == o.H && K == o.K &&
            chunk == o.chunk && wgs == o.wgs && op == o.op && step_policy == o.step_policy && split == o.split &&
-           out == o.out;
+           out == o.out && sub == o.sub;
   }
 };
 struct GraphSlot {
@@ -81,6 +111,9 @@ struct bc_ctx {
   int K = 0;
   double vmin = 0, vmax = 1, dt_ref = 1;
   std::vector<bc_view> views;
+  int64_t view_tiles = 0;          // host bound on the sub-image tiles the views need
+  float4* static_sub = nullptr;    // this device's copy of `scratch`
+  std::vector<float> occ_key;      // per-frame classification key (sized with the table)
   // kernel launch shape and options
   int render_workgroups = 0;
   bool ess = true;
@@ -333,8 +366,8 @@ BcFramePtrs pass_ptrs(bc_ctx* c, BcFramePtrs f, int pass, int width, int height)
 }
 
 // the same pass on the second set of per-pass arrays, with the sub-image
-// tiles [first, first + cap) of the shared buffer
-BcFramePtrs second_slot(bc_ctx* c, BcFramePtrs f, int64_t first, int64_t cap) {
+// tiles [first, first + cap) of the shared buffer `sub`
+BcFramePtrs second_slot(bc_ctx* c, BcFramePtrs f, float4* sub, int64_t first, int64_t cap) {
   char* meta = static_cast<char*>(c->dev[1]);
   f.views = reinterpret_cast<BcViewParams*>(meta + c->off_views_b);
   f.order = reinterpret_cast<int32_t*>(meta + c->off_order_b);
@@ -342,7 +375,7 @@ BcFramePtrs second_slot(bc_ctx* c, BcFramePtrs f, int64_t first, int64_t cap) {
   f.item_base = reinterpret_cast<int32_t*>(meta + c->off_item_base_b);
   f.item_perm = reinterpret_cast<int32_t*>(meta + c->off_item_perm_b);
   f.ctr = reinterpret_cast<BcCounters*>(meta + c->off_ctr_b);
-  f.sub = static_cast<float4*>(c->dev[2]) + first * BC_TILE * BC_TILE;
+  f.sub = sub + first * BC_TILE * BC_TILE;
   f.max_items = cap;
   return f;
 }
@@ -431,6 +464,13 @@ int bc_create(int hip_device, bc_ctx** out) {
     ok = ok && hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
       g_create_error = "bc_create: cannot allocate pinned frame buffers / events";
+      bc_destroy(c);
+      return BC_E_HIP;
+    }
+    hipError_t se = hipSuccess;
+    c->static_sub = static_scratch(hip_device, &se);
+    if (!c->static_sub) {
+      g_create_error = std::string("bc_create: hipGetSymbolAddress(scratch): ") + hipGetErrorString(se);
       bc_destroy(c);
       return BC_E_HIP;
     }
@@ -578,6 +618,11 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
   c->planned = true;
   c->loaded = false;
   c->occ_valid = false;
+  if (c->has_view) {
+    int64_t tiles = 0;
+    for (const bc_view& v : c->views) tiles += view_tiles_bound(c, v);
+    c->view_tiles = tiles;
+  }
   return BC_OK;
 }
 
@@ -703,6 +748,7 @@ int bc_set_transfer_function(bc_ctx* c, const float* rgba, int K, double vmin, d
     if (!(rgba[i] >= 0.0f && rgba[i] <= 1.0f))
       return fail(c, BC_E_ARG, "bc_set_transfer_function: entry %d channel %d = %g outside [0, 1]", i / 4, i % 4, (double)rgba[i]);
   c->tf.assign(rgba, rgba + 4 * K);
+  c->occ_key.reserve(K + 4);
   c->K = K;
   c->vmin = vmin;
   c->vmax = vmax;
@@ -734,14 +780,27 @@ int bc_set_view(bc_ctx* c, const bc_view* views, int n) {
       return fail(c, BC_E_NOMEM, "bc_set_view: the views need up to %lld sub-image tiles, %lld planned",
                   (long long)tiles, (long long)c->max_tiles);
   }
+  {
+    int64_t tiles = 0;
+    for (int i = 0; i < n; ++i) tiles += view_tiles_bound(c, views[i]);
+    c->view_tiles = tiles;
+  }
   c->views.assign(views, views + n);
   c->has_view = true;
   return BC_OK;
 }
 
-int bc_render_frame(bc_ctx* c, float* out, void* stream) {
-  if (!c) return BC_E_ARG;
-  c->err.clear();
+}  // extern "C"
+
+namespace {
+
+// One frame: bc_render_frame with the bound sub-image region, or
+// bc_render_frame_static (no_alloc) with this device's `scratch`.  `sub` holds
+// sub_cap tiles.  With no_alloc nothing is allocated on the host or the device:
+// the kernels are launched directly (no graph of the library's own, since
+// instantiating one allocates) and the frame is not timed (timing creates its
+// events on demand).
+int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_cap, bool no_alloc) {
   if (c->device < 0) return fail(c, BC_E_STATE, "bc_render_frame: host-only context");
   if (!c->bound || !c->loaded) return fail(c, BC_E_STATE, "bc_render_frame: bricks not loaded");
   if (!c->has_tf) return fail(c, BC_E_STATE, "bc_render_frame: no transfer function");
@@ -791,7 +850,9 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
   // first entry) and on the value-to-table mapping: redo it when that changes
   bool classify = false;
   if (c->ess) {
-    std::vector<float> key(c->K + 4);
+    // (sized for this table by bc_set_transfer_function: no allocation here)
+    std::vector<float>& key = c->occ_key;
+    key.resize(c->K + 4);
     key[0] = (float)c->K;
     key[1] = pins[0].tf_scale;
     key[2] = pins[0].tf_bias;
@@ -819,10 +880,10 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
       coarse_tiles += view_tiles_bound(c, c->views[i], W / 2, H / 2, 1);
       val_tiles += view_tiles_bound(c, c->views[i], W, H, c->val_stride);
     }
-    if (val_tiles > 0 && coarse_tiles + val_tiles <= c->max_tiles) split = val_tiles;
+    if (val_tiles > 0 && coarse_tiles + val_tiles <= sub_cap) split = val_tiles;
   }
   hipEvent_t* ev = nullptr;
-  if (c->timing && c->timed_frames < kMaxTimedFrames) {
+  if (c->timing && !no_alloc && c->timed_frames < kMaxTimedFrames) {
     const size_t need = 4 * (size_t)(c->timed_frames + 1);
     while (c->tev.size() < need) {
       hipEvent_t e;
@@ -833,6 +894,8 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     ++c->timed_frames;
   }
   BcFramePtrs f = frame_ptrs(c);
+  f.sub = sub;
+  f.max_items = sub_cap;
   if (classify) {
     HIPCHECK(c, hipMemcpyAsync(meta + c->off_fin, pins, fin_bytes, hipMemcpyHostToDevice, st));
     HIPCHECK(c, bc_launch_classify(f, c->max_occ_words, st));
@@ -861,10 +924,10 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
         // tiles and workgroups, while the coarse pass and the network run
         const int val_wgs = (int)std::min<int64_t>((split + 3) / 4, std::max(c->render_workgroups / 4, 1));
         const int main_wgs = std::max(c->render_workgroups - val_wgs, 1);
-        BcFramePtrs fvb = second_slot(c, fv, c->max_tiles - split, split);
+        BcFramePtrs fvb = second_slot(c, fv, sub, sub_cap - split, split);
         // few long items that gate the frame, beside the whole coarse pass
         fvb.urgent = 1;
-        fc.max_items = c->max_tiles - split;
+        fc.max_items = sub_cap - split;
         HIPCHECK(c, hipEventRecord(c->fork_ev, s));
         HIPCHECK(c, hipStreamWaitEvent(c->aux_stream, c->fork_ev, 0));
         HIPCHECK(c, bc_launch_setup(fvb, c->aux_stream));
@@ -902,7 +965,7 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     if (e) HIPCHECK(c, hipEventRecord(e[3], s));
     return BC_OK;
   };
-  if (!c->use_graph) {
+  if (!c->use_graph || no_alloc) {
     int r = enqueue(st, ev);
     if (r) return r;
   } else {
@@ -922,6 +985,7 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
     key.step_policy = c->step_policy;
     key.split = split;
     key.out = out;
+    key.sub = sub;
     GraphSlot& g = c->graphs[slot];
     if (!g.exec || !(g.key == key)) {
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -960,6 +1024,28 @@ int bc_render_frame(bc_ctx* c, float* out, void* stream) {
   c->frame_pending = true;
   c->last_learned = c->learned;
   return BC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bc_render_frame(bc_ctx* c, float* out, void* stream) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  return render_impl(c, out, stream, static_cast<float4*>(c->dev[2]), c->max_tiles, false);
+}
+
+int bc_render_frame_static(bc_ctx* c, float* out, void* stream) {
+  if (!c) return BC_E_ARG;
+  c->err.clear();
+  if (c->device < 0) return fail(c, BC_E_STATE, "bc_render_frame_static: host-only context");
+  if (!c->static_sub) return fail(c, BC_E_STATE, "bc_render_frame_static: no static sub-image array on this device");
+  if (c->bound && c->has_view && c->view_tiles > BC_STATIC_MAX_TILES)
+    return fail(c, BC_E_NOMEM,
+                "bc_render_frame_static: the views need up to %lld sub-image tiles, the static array holds %d",
+                (long long)c->view_tiles, BC_STATIC_MAX_TILES);
+  return render_impl(c, out, stream, c->static_sub, std::min<int64_t>(c->max_tiles, BC_STATIC_MAX_TILES), true);
 }
 
 int bc_set_learned(bc_ctx* c, int enable, double coarse_step, double psnr_threshold_db, int validate_stride) {
