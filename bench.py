@@ -62,19 +62,21 @@ HBM_PEAK_GBS = 8000.0
 ORBIT = 64
 
 # HBM bytes per launch of the ray-casting kernel, measured with rocprofv3
-# counters (FETCH_SIZE x 2 + WRITE_SIZE x 1, KiB, the scales a plain 1 GiB
-# device copy reads back), mean over the render launches of
-# `bench.py --warmup 0 --repeats 0 --cpu-seconds 0 --check-pixels 0 [options]`
-# (the 64-frame orbit, twice).  Valid only for the kernel sources whose SHA-256
-# is recorded; any other source reports null.
+# counters: DRAM reads TCC_EA0_RDREQ_DRAM_32B x 32 plus DRAM writes
+# TCC_EA0_WRREQ_WRITE_DRAM_32B x 32 (both count 32-byte units; on a plain
+# 1 GiB device copy they read back 1.000 GiB each, so no scale is applied),
+# mean over the render launches of
+# `bench.py --warmup 0 --repeats 0 --cpu-seconds 0 --check-pixels 0 --forms 0
+# [options]` (the 64-frame orbit, twice).  Valid only for the kernel sources
+# whose SHA-256 is recorded; any other source reports null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "7e59b42cabf510622c82cb5454ccafba5bc1845b2213816495467f61037da748",
+    "sources_sha256": "1ee4487f01ff05fdea0cfb12d7142fb3f6a0f4e9ede1eeaf0cdfbaf91e2c9997",
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
-        "cube1024_persp1920x1080/f32/composite/fixed": 2360906321,
-        "cube1024_persp1920x1080/f32/mip/voxel": 2453292633,
-        "cube1024_persp1920x1080/f16/composite/fixed": 1487578767,
-        "cube1024_persp1920x1080/fp8/composite/fixed": 1003325781,
-        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 52033739477,
+        "cube1024_persp1920x1080/f32/composite/fixed": 2356701632,
+    },
+    # L2 (TCC) hit rate over the same launches: TCC_HIT / (TCC_HIT + TCC_MISS)
+    "l2_hit_rate": {
+        "cube1024_persp1920x1080/f32/composite/fixed": 0.7765,
     },
 }
 KERNEL_SOURCES = ("bc_render.hip", "bc_types.h", "bc_kernels.h", "bc_df.h", "bc_e4m3.h")
@@ -89,10 +91,10 @@ def kernel_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(key: str):
+def measured_traffic(key: str, what: str = "bytes"):
     if MEASURED_TRAFFIC["sources_sha256"] != kernel_sha256():
         return None
-    return MEASURED_TRAFFIC["bytes"].get(key)
+    return MEASURED_TRAFFIC[what].get(key)
 
 WORKLOADS = {
     # name: (recipe, brick edge, width, height, views per launch, source dtype)
@@ -579,7 +581,8 @@ def main():
         stage_ms = [m * n_timed for m in stage_ms_eager]
     render_s = stage_ms[1] / 1e3
     achieved = tot_bytes / render_s / 1e9
-    traffic = measured_traffic(f"{args.workload}/{args.storage}/{args.op}/{args.step_policy}")
+    key = f"{args.workload}/{args.storage}/{args.op}/{args.step_policy}"
+    traffic, l2_hit = measured_traffic(key), measured_traffic(key, "l2_hit_rate")
     result = {
         "metric": (f"Gsamples/s + fps @{W}x{H} on "
                    + ("1024^3 cube" if recipe.dims == (1024, 1024, 1024) else "x".join(map(str, recipe.dims)) + " cube")
@@ -619,7 +622,8 @@ def main():
             "kernel": "render_kernel", "algo_bytes_per_launch": tot_bytes / args.steps,
             # HBM bytes actually moved (counters), as a bandwidth and a fraction of peak
             "traffic_gbs": None if traffic is None else traffic / (render_s / args.steps) / 1e9,
-            "traffic_frac": None if traffic is None else traffic / (render_s / args.steps) / 1e9 / HBM_PEAK_GBS},
+            "traffic_frac": None if traffic is None else traffic / (render_s / args.steps) / 1e9 / HBM_PEAK_GBS,
+            "l2_hit_rate": l2_hit},
         "paper_statistic": paper_stat,
         "precision_vs_oracle": precision,
         "learned": learned,

@@ -674,18 +674,34 @@ int bc_load_bricks(bc_ctx* c, const void* src, const int64_t strides[3], int src
   BcCounters* ctr = reinterpret_cast<BcCounters*>(meta + c->off_ctr);
   hipStream_t st = nullptr;
   HIPCHECK(c, bc_launch_init_minmax(ctr, c->n_bricks, st));
-  for (int b = 0; b < c->n_bricks; ++b) {
+  // launch bounds: the largest brick's ghosted rows and micro-block rows
+  int max_rows = 0;
+  int64_t max_mb_rows = 0;
+  for (const BcBrick& hb : c->bricks) {
+    max_rows = std::max(max_rows, (hb.hi[1] - hb.lo[1] + 2) * (hb.hi[2] - hb.lo[2] + 2));
+    max_mb_rows = std::max<int64_t>(max_mb_rows, (int64_t)hb.mb[0] * hb.mb[1] * hb.mb[2] * 16);
+  }
+  if (src_on_device) {
+    // the whole share is on the device: every brick in one launch per step
+    BcLoadSrc s;
+    s.dtype = d.src_dtype == BC_F32 ? 0 : 1;
+    s.ptr = src;
+    for (int a = 0; a < 3; ++a) {
+      s.dims[a] = (int32_t)d.global_dims[a];
+      s.strides[a] = strides[a];
+      s.origin[a] = (int32_t)box_lo[a];
+    }
+    HIPCHECK(c, bc_launch_minmax(s, dbricks, 0, c->n_bricks, max_rows, ctr, st));
+    HIPCHECK(c, bc_launch_finalize(dbricks, ctr, 0, c->n_bricks, d.storage, st));
+    HIPCHECK(c, bc_launch_encode(s, dbricks, 0, c->n_bricks, max_mb_rows, d.storage, c->dev[0], st));
+  }
+  // a host source goes through the load scratch region one brick at a time
+  for (int b = 0; b < c->n_bricks && !src_on_device; ++b) {
     const BcBrick& hb = c->bricks[b];
     BcLoadSrc s;
     s.dtype = d.src_dtype == BC_F32 ? 0 : 1;
     for (int a = 0; a < 3; ++a) s.dims[a] = (int32_t)d.global_dims[a];
-    if (src_on_device) {
-      s.ptr = src;
-      for (int a = 0; a < 3; ++a) {
-        s.strides[a] = strides[a];
-        s.origin[a] = (int32_t)box_lo[a];
-      }
-    } else {
+    {
       // gather the brick's ghosted region (clamped to the cube) into pinned
       // staging, then copy it into the scratch region
       int64_t rlo[3], rhi[3];
@@ -723,11 +739,10 @@ int bc_load_bricks(bc_ctx* c, const void* src, const int64_t strides[3], int src
       s.strides[2] = rx * ry;
       for (int a = 0; a < 3; ++a) s.origin[a] = (int32_t)rlo[a];
     }
-    HIPCHECK(c, bc_launch_minmax(s, hb.lo, hb.hi, ctr, b, st));
+    HIPCHECK(c, bc_launch_minmax(s, dbricks, b, 1, max_rows, ctr, st));
     HIPCHECK(c, bc_launch_finalize(dbricks, ctr, b, 1, d.storage, st));
-    const int64_t n_elems = (int64_t)hb.mb[0] * hb.mb[1] * hb.mb[2] * BC_MB_ELEMS;
-    HIPCHECK(c, bc_launch_encode(s, dbricks, b, n_elems, d.storage, c->dev[0], st));
-    if (!src_on_device) HIPCHECK(c, hipStreamSynchronize(st));
+    HIPCHECK(c, bc_launch_encode(s, dbricks, b, 1, max_mb_rows, d.storage, c->dev[0], st));
+    HIPCHECK(c, hipStreamSynchronize(st));
   }
   HIPCHECK(c, hipStreamSynchronize(st));
   HIPCHECK(c, hipMemcpy(c->bricks.data(), dbricks, sizeof(BcBrick) * c->n_bricks, hipMemcpyDeviceToHost));

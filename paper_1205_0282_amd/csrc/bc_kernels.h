@@ -13,11 +13,13 @@ struct BcLoadSrc {
 };
 
 hipError_t bc_launch_init_minmax(BcCounters* ctr, int n, hipStream_t st);
-hipError_t bc_launch_minmax(const BcLoadSrc& src, const int32_t lo[3], const int32_t hi[3],
-                            BcCounters* ctr, int b, hipStream_t st);
+// bricks [first, first + count): max_rows bounds each brick's ghosted rows
+// (y * z extent); the encode's max_rows bounds its micro-block rows
+hipError_t bc_launch_minmax(const BcLoadSrc& src, const BcBrick* bricks, int first, int count, int max_rows,
+                            BcCounters* ctr, hipStream_t st);
 hipError_t bc_launch_finalize(BcBrick* bricks, const BcCounters* ctr, int first, int count, int storage,
                               hipStream_t st);
-hipError_t bc_launch_encode(const BcLoadSrc& src, const BcBrick* bricks, int b, int64_t n_elems,
+hipError_t bc_launch_encode(const BcLoadSrc& src, const BcBrick* bricks, int first, int count, int64_t max_rows,
                             int storage, void* pool, hipStream_t st);
 
 struct BcFramePtrs {

@@ -40,27 +40,35 @@ __device__ __forceinline__ float src_at(const SrcView& s, int gx, int gy, int gz
   return to_f32<T>(p[(int64_t)(gx - s.ox) * s.sx + (int64_t)(gy - s.oy) * s.sy + (int64_t)(gz - s.oz) * s.sz]);
 }
 
-// min/max over the brick's ghosted region [lo-1, hi+1) (clamped to the cube)
+// min/max over each brick's ghosted region [lo-1, hi+1) (clamped to the
+// cube): brick first + blockIdx.y; every wave takes whole rows along x (32-bit
+// index arithmetic, coalesced loads) and folds them into the brick's pair
 template <typename T>
-__global__ __launch_bounds__(256) void minmax_kernel(SrcView s, int3 lo, int3 ext, uint32_t* out) {
-  const int64_t total = (int64_t)ext.x * ext.y * ext.z;
+__global__ __launch_bounds__(256) void minmax_kernel(SrcView s, const BcBrick* __restrict__ bricks, int first,
+                                                     BcCounters* ctr) {
+  const int b = first + (int)blockIdx.y;
+  const BcBrick& br = bricks[b];
+  const int ex = br.hi[0] - br.lo[0] + 2, ey = br.hi[1] - br.lo[1] + 2, ez = br.hi[2] - br.lo[2] + 2;
+  const int rows = ey * ez;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int n_waves = (int)(gridDim.x * (blockDim.x >> 6));
   float mn = INFINITY, mx = -INFINITY;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int x = (int)(e % ext.x);
-    const int y = (int)((e / ext.x) % ext.y);
-    const int z = (int)(e / ((int64_t)ext.x * ext.y));
-    const float v = src_at<T>(s, lo.x - 1 + x, lo.y - 1 + y, lo.z - 1 + z);
-    mn = fminf(mn, v);
-    mx = fmaxf(mx, v);
+  for (int r = wave; r < rows; r += n_waves) {
+    const int y = r % ey, z = r / ey;
+    for (int x = lane; x < ex; x += 64) {
+      const float v = src_at<T>(s, br.lo[0] - 1 + x, br.lo[1] - 1 + y, br.lo[2] - 1 + z);
+      mn = fminf(mn, v);
+      mx = fmaxf(mx, v);
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     mn = fminf(mn, __shfl_xor(mn, off));
     mx = fmaxf(mx, __shfl_xor(mx, off));
   }
-  if ((threadIdx.x & 63) == 0) {
-    atomicMin(&out[0], ordered_bits(mn));
-    atomicMax(&out[1], ordered_bits(mx));
+  if (lane == 0 && mn <= mx) {
+    atomicMin(&ctr->minmax[b][0], ordered_bits(mn));
+    atomicMax(&ctr->minmax[b][1], ordered_bits(mx));
   }
 }
 
@@ -103,36 +111,36 @@ __global__ void finalize_kernel(BcBrick* bricks, const BcCounters* ctr, int firs
   bricks[b].dmax = dmax;
 }
 
+// encode + layout: brick first + blockIdx.y; one thread per micro-block row
+// (5 stored elements), 32-bit index arithmetic
 template <typename T, int FMT>
-__global__ __launch_bounds__(256) void encode_kernel(SrcView s, const BcBrick* bricks, int b, void* pool) {
-  const BcBrick br = bricks[b];
-  const int64_t total = (int64_t)br.mb[0] * br.mb[1] * br.mb[2] * BC_MB_ELEMS;
+__global__ __launch_bounds__(256) void encode_kernel(SrcView s, const BcBrick* __restrict__ bricks, int first,
+                                                     void* pool) {
+  const BcBrick& br = bricks[first + (int)blockIdx.y];
+  const int mb0 = br.mb[0], mb1 = br.mb[1];
+  const int n_rows = mb0 * mb1 * br.mb[2] * 16;
   const int cx = br.hi[0] - br.lo[0], cy = br.hi[1] - br.lo[1], cz = br.hi[2] - br.lo[2];
-  const float inv = 1.0f / br.scale;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t mbi = e / BC_MB_ELEMS;
-    const int in = (int)(e - mbi * BC_MB_ELEMS);
-    const int mbx = (int)(mbi % br.mb[0]);
-    const int mby = (int)((mbi / br.mb[0]) % br.mb[1]);
-    const int mbz = (int)(mbi / ((int64_t)br.mb[0] * br.mb[1]));
-    const int row = in / BC_ROW;
-    const int wx = in - row * BC_ROW;   // 0..4: the fifth repeats the next micro-block's first voxel
-    const int wy = row & 3;
-    const int wz = row >> 2;
+  const float inv = 1.0f / br.scale, offs = br.offs;
+  for (int idx = (int)(blockIdx.x * blockDim.x + threadIdx.x); idx < n_rows; idx += (int)(gridDim.x * blockDim.x)) {
+    const int mbi = idx >> 4, row = idx & 15;
+    const int t = mbi / mb0;
+    const int mbx = mbi - t * mb0, mby = t % mb1, mbz = t / mb1;
     // local ghosted index (0 <-> voxel lo-1); padding replicates the last ghost
-    const int lx = min(mbx * 4 + wx, cx + 1);
-    const int ly = min(mby * 4 + wy, cy + 1);
-    const int lz = min(mbz * 4 + wz, cz + 1);
-    const float v = src_at<T>(s, br.lo[0] - 1 + lx, br.lo[1] - 1 + ly, br.lo[2] - 1 + lz);
-    const int64_t dst = br.offset + e;
-    if (FMT == 0) {
-      static_cast<float*>(pool)[dst] = v;
-    } else if (FMT == 1) {
-      static_cast<__half*>(pool)[dst] = __float2half_rn(v);
-    } else {
-      const float xq = (v - br.offs) * inv;
-      static_cast<uint8_t*>(pool)[dst] = bc_e4m3_encode(xq);
+    const int ly = min(mby * 4 + (row & 3), cy + 1);
+    const int lz = min(mbz * 4 + (row >> 2), cz + 1);
+    const int64_t dst = br.offset + (int64_t)mbi * BC_MB_ELEMS + row * BC_ROW;
+#pragma unroll
+    for (int wx = 0; wx < BC_ROW; ++wx) {   // the fifth repeats the next micro-block's first voxel
+      const int lx = min(mbx * 4 + wx, cx + 1);
+      const float v = src_at<T>(s, br.lo[0] - 1 + lx, br.lo[1] - 1 + ly, br.lo[2] - 1 + lz);
+      if (FMT == 0) {
+        static_cast<float*>(pool)[dst + wx] = v;
+      } else if (FMT == 1) {
+        static_cast<__half*>(pool)[dst + wx] = __float2half_rn(v);
+      } else {
+        const float xq = (v - offs) * inv;
+        static_cast<uint8_t*>(pool)[dst + wx] = bc_e4m3_encode(xq);
+      }
     }
   }
 }
@@ -153,17 +161,14 @@ hipError_t bc_launch_init_minmax(BcCounters* ctr, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t bc_launch_minmax(const BcLoadSrc& src, const int32_t lo[3], const int32_t hi[3],
-                            BcCounters* ctr, int b, hipStream_t st) {
+hipError_t bc_launch_minmax(const BcLoadSrc& src, const BcBrick* bricks, int first, int count, int max_rows,
+                            BcCounters* ctr, hipStream_t st) {
   SrcView s = make_src(src);
-  int3 l = make_int3(lo[0], lo[1], lo[2]);
-  int3 ext = make_int3(hi[0] - lo[0] + 2, hi[1] - lo[1] + 2, hi[2] - lo[2] + 2);
-  const int64_t total = (int64_t)ext.x * ext.y * ext.z;
-  int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  const dim3 grid((unsigned)std::max(1, std::min((max_rows + 3) / 4, 64)), (unsigned)count);
   if (src.dtype == 0)
-    minmax_kernel<float><<<grid, 256, 0, st>>>(s, l, ext, ctr->minmax[b]);
+    minmax_kernel<float><<<grid, 256, 0, st>>>(s, bricks, first, ctr);
   else
-    minmax_kernel<__half><<<grid, 256, 0, st>>>(s, l, ext, ctr->minmax[b]);
+    minmax_kernel<__half><<<grid, 256, 0, st>>>(s, bricks, first, ctr);
   return hipGetLastError();
 }
 
@@ -173,18 +178,18 @@ hipError_t bc_launch_finalize(BcBrick* bricks, const BcCounters* ctr, int first,
   return hipGetLastError();
 }
 
-hipError_t bc_launch_encode(const BcLoadSrc& src, const BcBrick* bricks, int b, int64_t n_elems,
+hipError_t bc_launch_encode(const BcLoadSrc& src, const BcBrick* bricks, int first, int count, int64_t max_rows,
                             int storage, void* pool, hipStream_t st) {
   SrcView s = make_src(src);
-  int grid = (int)std::min<int64_t>((n_elems + 255) / 256, 8192);
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((max_rows + 255) / 256, 256)), (unsigned)count);
   if (src.dtype == 0) {
-    if (storage == 0) encode_kernel<float, 0><<<grid, 256, 0, st>>>(s, bricks, b, pool);
-    else if (storage == 1) encode_kernel<float, 1><<<grid, 256, 0, st>>>(s, bricks, b, pool);
-    else encode_kernel<float, 2><<<grid, 256, 0, st>>>(s, bricks, b, pool);
+    if (storage == 0) encode_kernel<float, 0><<<grid, 256, 0, st>>>(s, bricks, first, pool);
+    else if (storage == 1) encode_kernel<float, 1><<<grid, 256, 0, st>>>(s, bricks, first, pool);
+    else encode_kernel<float, 2><<<grid, 256, 0, st>>>(s, bricks, first, pool);
   } else {
-    if (storage == 0) encode_kernel<__half, 0><<<grid, 256, 0, st>>>(s, bricks, b, pool);
-    else if (storage == 1) encode_kernel<__half, 1><<<grid, 256, 0, st>>>(s, bricks, b, pool);
-    else encode_kernel<__half, 2><<<grid, 256, 0, st>>>(s, bricks, b, pool);
+    if (storage == 0) encode_kernel<__half, 0><<<grid, 256, 0, st>>>(s, bricks, first, pool);
+    else if (storage == 1) encode_kernel<__half, 1><<<grid, 256, 0, st>>>(s, bricks, first, pool);
+    else encode_kernel<__half, 2><<<grid, 256, 0, st>>>(s, bricks, first, pool);
   }
   return hipGetLastError();
 }

@@ -117,6 +117,14 @@ __device__ __forceinline__ uint32_t vox_index(int x, int y, int z, int mbx, int 
   return mad_u24(blk, BC_MB_ELEMS, in_blk);
 }
 
+// (a & mask) | (b & ~mask) in one instruction (the compiler splits the
+// expression into ands and ors)
+__device__ __forceinline__ uint32_t bfi_u32(uint32_t mask, uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(mask), "v"(a), "v"(b));
+  return r;
+}
+
 // a * b + c on signed 24-bit a and b (one multiply-add instruction)
 __device__ __forceinline__ int mad_i24(int a, int b, int c) { return __mul24(a, b) + c; }
 
@@ -492,7 +500,8 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
               // word (x/4, y/4, z/2) as a byte offset; bit (x%4) + 4 (y%4) + 16 (z%2), of
               // which the bit-field extract below reads only the low five bits
               wofs[i] = mad_u24(mad_u24(iz16 >> 5, WY, iy4 >> 4), WX4, ix & ~3u);
-              bit[i] = (((ix & 3u) | (iy4 & ~3u)) & 15u) | (iz16 & ~15u);
+              // two bit-field inserts: x%4 into 4 (y%4), then into 16 (z%2)
+              bit[i] = bfi_u32(15u, bfi_u32(3u, ix, iy4), iz16);
               un0 += s0; un1 += s1q; un2 += s2q;
             }
             // a sample in the same word as the one before it reuses that
