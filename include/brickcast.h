@@ -244,21 +244,29 @@ int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);
  *    whole bricks (brick b in queue b % 8), each served first by the
  *    workgroups of one XCD, so that the eight L2 caches hold different bricks;
  *    0 uses a single queue.  Images do not depend on it.
+ *  BC_OPT_TILE_WIDTH (4, 8 or 16; default 8): width in pixels of the screen
+ *    tile one wave casts (its 64 rays): 4 x 16, 8 x 8 or 16 x 4 pixels.
+ *    Rendering rectangles and work items are counted in these tiles.  Images
+ *    do not depend on it.  BC_E_NOMEM (shape unchanged) if the current views
+ *    would need more sub-image tiles than planned with this shape.
  * Errors: BC_E_ARG for an unknown option or a value out of range. */
 enum bc_option { BC_OPT_EMPTY_SKIP = 0, BC_OPT_RENDER_WORKGROUPS = 1, BC_OPT_SAMPLE_CHUNK = 2, BC_OPT_GRAPH = 3,
-                 BC_OPT_XCD_QUEUES = 4 };
+                 BC_OPT_XCD_QUEUES = 4, BC_OPT_TILE_WIDTH = 5 };
 int bc_set_option(bc_ctx* ctx, int option, int64_t value);
 
 /* Autotuner: renders the current views (plain frames) with every candidate
- * launch shape -- samples per occupancy chunk in {32, 64} times persistent
- * workgroups in {2, 4, 6, 8} per compute unit -- for `frames` timed frames each
- * (after one warm-up frame per candidate), measures the ray-casting kernel with
- * HIP events and keeps the fastest; chosen[0] = chunk, chosen[1] = workgroups
- * (chosen may be NULL).  Writes frames into `out` (same contract as
- * bc_render_frame) and waits for them.  The result applies to later frames
- * (also settable with bc_set_option).  Errors: as bc_render_frame; BC_E_ARG
- * for frames outside [1, 64]; BC_E_STATE with learned frames on. */
-int bc_autotune(bc_ctx* ctx, float* out, void* stream, int frames, int64_t chosen[2]);
+ * launch shape -- screen tiles of 8 x 8, 16 x 4 and 4 x 16 pixels (those whose
+ * work items fit the planned sub-image tiles) times samples per occupancy chunk
+ * in {32, 64} times persistent workgroups in {2, 4, 6, 8} per compute unit --
+ * for `frames` timed frames each (after one warm-up frame per candidate),
+ * measures the ray-casting kernel with HIP events and keeps the fastest;
+ * chosen[0] = chunk, chosen[1] = workgroups, chosen[2] = tile width in pixels
+ * (chosen may be NULL; else it has 3 entries).  Writes frames into `out` (same
+ * contract as bc_render_frame) and waits for them.  The result applies to
+ * later frames (also settable with bc_set_option).  Errors: as
+ * bc_render_frame; BC_E_ARG for frames outside [1, 64]; BC_E_STATE with
+ * learned frames on. */
+int bc_autotune(bc_ctx* ctx, float* out, void* stream, int frames, int64_t chosen[3]);
 
 /* Per-stage GPU time, measured with HIP events recorded on the frame's own
  * stream.  bc_enable_timing(ctx, 1) waits for the last frame and opens a new
@@ -284,8 +292,9 @@ int bc_get_frame_times(bc_ctx* ctx, double* ms, int cap, int* n_frames);
 int bc_get_bricks(bc_ctx* ctx, int32_t* lo_hi, float* scale_offset, float* min_max, int cap, int* n);
 
 /* Visibility order (front to back brick indices) and rendering rectangles
- * (x0, y0, x1, y1 half-open pixel bounds, already widened to whole 8x8 tiles)
- * of `view` in the last frame; waits for it to finish. */
+ * (x0, y0, x1, y1 half-open pixel bounds, already widened to whole screen
+ * tiles of the last frame's shape) of `view` in the last frame; waits for it
+ * to finish. */
 int bc_get_visibility_order(bc_ctx* ctx, int view, int32_t* order, int cap);
 int bc_get_rects(bc_ctx* ctx, int view, int32_t* rects, int cap);
 

@@ -31,6 +31,7 @@ EXPORTS = [
 BC_STATIC_MAX_TILES = 65536
 CNN_N_PARAMS = 15056
 BC_OPT_EMPTY_SKIP, BC_OPT_RENDER_WORKGROUPS, BC_OPT_SAMPLE_CHUNK, BC_OPT_GRAPH, BC_OPT_XCD_QUEUES = 0, 1, 2, 3, 4
+BC_OPT_TILE_WIDTH = 5
 BC_OP_COMPOSITE, BC_OP_MIP = 0, 1
 BC_STEP_FIXED, BC_STEP_PER_VOXEL = 0, 1
 
@@ -260,15 +261,15 @@ class BrickCaster:
 
     def autotune(self, out=None, frames=3, stream=None):
         """Times every candidate launch shape on the current views and keeps
-        the fastest; returns (chunk, workgroups)."""
+        the fastest; returns (chunk, workgroups, tile width)."""
         import torch
         if out is None:
             out = torch.empty((self.n_views, self.height, self.width, 4), dtype=torch.float32,
                               device=torch.device("cuda", self.device))
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
-        ch = (C.c_int64 * 2)()
+        ch = (C.c_int64 * 3)()
         self._check(self.lib.bc_autotune(self.h, C.c_void_p(out.data_ptr()), C.c_void_p(st), int(frames), ch))
-        return int(ch[0]), int(ch[1])
+        return int(ch[0]), int(ch[1]), int(ch[2])
 
     def set_operator(self, op="composite", step="fixed"):
         """op: "composite" or "mip"; step: "fixed" (the views' step) or "voxel"

@@ -24,7 +24,7 @@
 // the library runs on holds its own copy until the process ends.  In host code
 // the name is only a stand-in: kernels are given the device address that
 // hipGetSymbolAddress returns for it (kept per device below), never the name.
-static __device__ __align__(256) float4 scratch[(size_t)BC_STATIC_MAX_TILES * BC_TILE * BC_TILE];
+static __device__ __align__(256) float4 scratch[(size_t)BC_STATIC_MAX_TILES * 64];
 
 namespace {
 
@@ -52,13 +52,14 @@ float4* static_scratch(int device, hipError_t* err) {
 
 struct GraphKey {
   bool learned = false, ess = false, xcd = false;
-  int n_views = 0, W = 0, H = 0, K = 0, chunk = 0, wgs = 0, op = 0, step_policy = 0;
+  int n_views = 0, W = 0, H = 0, K = 0, chunk = 0, wgs = 0, op = 0, step_policy = 0, tile_shift = 0;
   int64_t split = 0;   // learned frames: sub-image tiles set aside for the concurrent validation pass (0: serial)
   const void* out = nullptr;
   const void* sub = nullptr;   // sub-image tiles the launches write
   bool operator==(const GraphKey& o) const {
     return learned == o.learned && ess == o.ess && xcd == o.xcd && n_views == o.n_views && W == o.W && H == o.H && K == o.K &&
            chunk == o.chunk && wgs == o.wgs && op == o.op && step_policy == o.step_policy && split == o.split &&
+           tile_shift == o.tile_shift &&
            out == o.out && sub == o.sub;
   }
 };
@@ -116,6 +117,9 @@ struct bc_ctx {
   std::vector<float> occ_key;      // per-frame classification key (sized with the table)
   // kernel launch shape and options
   int render_workgroups = 0;
+  // screen tiles of (1 << tile_shift) x (64 >> tile_shift) pixels (8 x 8 by
+  // default); the shape of the last frame, for its rectangles
+  int tile_shift = 3, frame_tile_shift = 3;
   bool ess = true;
   bool xcd_queues = true;
   int chunk = 32;
@@ -238,7 +242,8 @@ int64_t view_tiles_bound(const bc_ctx* c, const bc_view& v, int W, int H, int st
   const bool persp = P[14] == -1.0;
   double eye[3];
   for (int a = 0; a < 3; ++a) eye[a] = -((M[a] * M[3] + M[4 + a] * M[7]) + M[8 + a] * M[11]);
-  const int TX = (W + BC_TILE - 1) / BC_TILE, TY = (H + BC_TILE - 1) / BC_TILE;
+  const int sx = c->tile_shift, sy = 6 - c->tile_shift;
+  const int TX = (W + (1 << sx) - 1) >> sx, TY = (H + (1 << sy) - 1) >> sy;
   // selected tiles among n consecutive ones, wherever the selection starts
   auto sel = [stride](int64_t n) -> int64_t { return (n + stride - 1) / stride; };
   int64_t total = 0;
@@ -264,8 +269,8 @@ int64_t view_tiles_bound(const bc_ctx* c, const bc_view& v, int W, int H, int st
     const int x0 = (int)std::max(std::floor(xmin) - 1.0, 0.0), y0 = (int)std::max(std::floor(ymin) - 1.0, 0.0);
     const int x1 = (int)std::min(std::ceil(xmax) + 1.0, (double)(W - 1)), y1 = (int)std::min(std::ceil(ymax) + 1.0, (double)(H - 1));
     if (x1 < x0 || y1 < y0) continue;
-    const int tx0 = std::max(x0 / BC_TILE - 1, 0), ty0 = std::max(y0 / BC_TILE - 1, 0);
-    const int tx1 = std::min(x1 / BC_TILE + 2, TX), ty1 = std::min(y1 / BC_TILE + 2, TY);
+    const int tx0 = std::max((x0 >> sx) - 1, 0), ty0 = std::max((y0 >> sy) - 1, 0);
+    const int tx1 = std::min((x1 >> sx) + 2, TX), ty1 = std::min((y1 >> sy) + 2, TY);
     total += sel(tx1 - tx0) * sel(ty1 - ty0);
   }
   return total;
@@ -288,6 +293,7 @@ BcFramePtrs frame_ptrs(bc_ctx* c) {
   f.occ = reinterpret_cast<uint32_t*>(meta + c->off_occ);
   f.ess = c->ess ? 1 : 0;
   f.chunk = c->chunk;
+  f.tile_shift = c->tile_shift;
   f.K = c->K;
   f.op = c->op;
   f.step_policy = c->step_policy;
@@ -375,7 +381,7 @@ BcFramePtrs second_slot(bc_ctx* c, BcFramePtrs f, float4* sub, int64_t first, in
   f.item_base = reinterpret_cast<int32_t*>(meta + c->off_item_base_b);
   f.item_perm = reinterpret_cast<int32_t*>(meta + c->off_item_perm_b);
   f.ctr = reinterpret_cast<BcCounters*>(meta + c->off_ctr_b);
-  f.sub = sub + first * BC_TILE * BC_TILE;
+  f.sub = sub + first * 64;
   f.max_items = cap;
   return f;
 }
@@ -583,7 +589,11 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
         max_words = std::max<int64_t>(max_words, words);
         max_region = std::max(max_region, (size_t)region);
       }
-  const int64_t tiles_frame = (int64_t)((max_w + BC_TILE - 1) / BC_TILE) * ((max_h + BC_TILE - 1) / BC_TILE);
+  // screen tiles of a frame, for the largest count over the tile shapes
+  int64_t tiles_frame = 0;
+  for (int s = 2; s <= 4; ++s)
+    tiles_frame = std::max<int64_t>(tiles_frame, (int64_t)((max_w + (1 << s) - 1) >> s) *
+                                                     ((max_h + (1 << (6 - s)) - 1) >> (6 - s)));
   if (max_tiles == 0) {
     // every brick over the whole frame when that is small, else a bound on how
     // many brick rectangles overlap a screen tile
@@ -612,7 +622,7 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
   c->off_occ = m; m = align256(m + sizeof(uint32_t) * (size_t)occ_words);
   c->bytes[1] = m;
   c->max_occ_words = (int)max_words;
-  c->bytes[2] = align256((size_t)max_tiles * BC_TILE * BC_TILE * 16);
+  c->bytes[2] = align256((size_t)max_tiles * 64 * 16);
   c->bytes[3] = align256(max_region * c->src_elem_bytes);
   for (int i = 0; i < 4; ++i) bytes_out[i] = c->bytes[i];
   c->planned = true;
@@ -822,6 +832,9 @@ int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_ca
   if (!c->has_view) return fail(c, BC_E_STATE, "bc_render_frame: no view");
   if (!out) return fail(c, BC_E_ARG, "bc_render_frame: out is NULL");
   if (reinterpret_cast<uintptr_t>(out) & 15) return fail(c, BC_E_ARG, "bc_render_frame: out not 16-byte aligned");
+  if (c->view_tiles > sub_cap)
+    return fail(c, BC_E_NOMEM, "bc_render_frame: the views need up to %lld sub-image tiles, %lld available",
+                (long long)c->view_tiles, (long long)sub_cap);
   const int n = (int)c->views.size();
   const int W = c->views[0].width, H = c->views[0].height;
   if (c->learned) {
@@ -860,6 +873,7 @@ int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_ca
   }
   const size_t fin_bytes = offsetof(BcFrameIn, table) + sizeof(float) * 4 * c->K;
   c->frame_views = n;
+  c->frame_tile_shift = c->tile_shift;
   // empty-space classification depends only on which table entries matter
   // (non-zero opacity; for maximum intensity projection, different from the
   // first entry) and on the value-to-table mapping: redo it when that changes
@@ -998,6 +1012,7 @@ int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_ca
     key.xcd = c->xcd_queues;
     key.op = c->op;
     key.step_policy = c->step_policy;
+    key.tile_shift = c->tile_shift;
     key.split = split;
     key.out = out;
     key.sub = sub;
@@ -1136,6 +1151,23 @@ int bc_set_option(bc_ctx* c, int option, int64_t value) {
       }
       c->use_graph = value != 0;
       return BC_OK;
+    case BC_OPT_TILE_WIDTH: {
+      if (value != 4 && value != 8 && value != 16)
+        return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_TILE_WIDTH takes 4, 8 or 16");
+      const int old = c->tile_shift;
+      c->tile_shift = value == 4 ? 2 : (value == 8 ? 3 : 4);
+      if (c->planned && c->has_view) {
+        int64_t tiles = 0;
+        for (const bc_view& v : c->views) tiles += view_tiles_bound(c, v);
+        if (tiles > c->max_tiles) {
+          c->tile_shift = old;
+          return fail(c, BC_E_NOMEM, "bc_set_option: with %lld-pixel-wide tiles the views need %lld sub-image tiles, "
+                      "%lld planned", (long long)value, (long long)tiles, (long long)c->max_tiles);
+        }
+        c->view_tiles = tiles;
+      }
+      return BC_OK;
+    }
     case BC_OPT_RENDER_WORKGROUPS:
       if (value < 1 || value > (1 << 20))
         return fail(c, BC_E_ARG, "bc_set_option: BC_OPT_RENDER_WORKGROUPS outside [1, 2^20]");
@@ -1146,53 +1178,69 @@ int bc_set_option(bc_ctx* c, int option, int64_t value) {
   }
 }
 
-int bc_autotune(bc_ctx* c, float* out, void* stream, int frames, int64_t chosen[2]) {
+int bc_autotune(bc_ctx* c, float* out, void* stream, int frames, int64_t chosen[3]) {
   if (!c) return BC_E_ARG;
   c->err.clear();
   if (frames < 1 || frames > 64) return fail(c, BC_E_ARG, "bc_autotune: frames outside [1, 64]");
   if (c->device < 0) return fail(c, BC_E_STATE, "bc_autotune: host-only context");
   if (c->learned) return fail(c, BC_E_STATE, "bc_autotune: tune with learned frames off");
+  if (!c->planned || !c->has_view) return fail(c, BC_E_STATE, "bc_autotune: plan and set the views first");
   HIPCHECK(c, hipSetDevice(c->device));
   int r = wait_frame(c);
   if (r) return r;
   const bool timing = c->timing, graph = c->use_graph;
-  const int chunk0 = c->chunk, wgs0 = c->render_workgroups;
+  const int chunk0 = c->chunk, wgs0 = c->render_workgroups, shift0 = c->tile_shift;
+  const int64_t tiles0 = c->view_tiles;
   c->use_graph = false;
+  const int shifts[3] = {3, 4, 2};   // 8 x 8, 16 x 4, 4 x 16 screen tiles
   const int chunks[2] = {32, 64};
   const int per_cu[4] = {2, 4, 6, 8};
   double best = 1e300;
-  int best_chunk = chunk0, best_wgs = wgs0;
+  int best_chunk = chunk0, best_wgs = wgs0, best_shift = shift0;
+  int64_t best_tiles = tiles0;
   // one untimed frame first: classification and caches
   r = bc_render_frame(c, out, stream);
-  for (int ci = 0; ci < 2 && !r; ++ci)
-    for (int wi = 0; wi < 4 && !r; ++wi) {
-      c->chunk = chunks[ci];
-      c->render_workgroups = c->n_cu * per_cu[wi];
-      c->timing = true;
-      c->timed_frames = 0;
-      for (int k = 0; k < frames + 1 && !r; ++k) {
-        if (k == 1) c->timed_frames = 0;   // the first frame of a candidate warms it up
-        r = bc_render_frame(c, out, stream);
+  for (int si = 0; si < 3 && !r; ++si) {
+    c->tile_shift = shifts[si];
+    int64_t tiles = 0;
+    for (const bc_view& v : c->views) tiles += view_tiles_bound(c, v);
+    if (tiles > c->max_tiles) continue;   // this shape does not fit the planned sub-image tiles
+    c->view_tiles = tiles;
+    for (int ci = 0; ci < 2 && !r; ++ci)
+      for (int wi = 0; wi < 4 && !r; ++wi) {
+        c->chunk = chunks[ci];
+        c->render_workgroups = c->n_cu * per_cu[wi];
+        c->timing = true;
+        c->timed_frames = 0;
+        for (int k = 0; k < frames + 1 && !r; ++k) {
+          if (k == 1) c->timed_frames = 0;   // the first frame of a candidate warms it up
+          r = bc_render_frame(c, out, stream);
+        }
+        if (r) break;
+        double ms[3];
+        int nf = 0;
+        r = bc_get_timing(c, ms, &nf);
+        if (!r && nf > 0 && ms[1] / nf < best) {
+          best = ms[1] / nf;
+          best_chunk = c->chunk;
+          best_wgs = c->render_workgroups;
+          best_shift = c->tile_shift;
+          best_tiles = c->view_tiles;
+        }
       }
-      if (r) break;
-      double ms[3];
-      int nf = 0;
-      r = bc_get_timing(c, ms, &nf);
-      if (!r && nf > 0 && ms[1] / nf < best) {
-        best = ms[1] / nf;
-        best_chunk = c->chunk;
-        best_wgs = c->render_workgroups;
-      }
-    }
+  }
   c->timing = timing;
   c->timed_frames = 0;
   c->use_graph = graph;
   c->chunk = r ? chunk0 : best_chunk;
   c->render_workgroups = r ? wgs0 : best_wgs;
+  c->tile_shift = r ? shift0 : best_shift;
+  c->view_tiles = r ? tiles0 : best_tiles;
   if (r) return r;
   if (chosen) {
     chosen[0] = best_chunk;
     chosen[1] = best_wgs;
+    chosen[2] = 1 << best_shift;
   }
   return BC_OK;
 }
@@ -1299,7 +1347,7 @@ int bc_get_rects(bc_ctx* c, int view, int32_t* rects, int cap) {
   HIPCHECK(c, hipMemcpy(rects, meta + c->off_rects + sizeof(int32_t) * 4 * view * c->n_bricks,
                         sizeof(int32_t) * 4 * c->n_bricks, hipMemcpyDeviceToHost));
   for (int b = 0; b < c->n_bricks; ++b)
-    for (int k = 0; k < 4; ++k) rects[4 * b + k] *= BC_TILE;
+    for (int k = 0; k < 4; ++k) rects[4 * b + k] *= (k & 1) ? (64 >> c->frame_tile_shift) : (1 << c->frame_tile_shift);
   return BC_OK;
 }
 

@@ -75,7 +75,7 @@ __device__ __forceinline__ void split(double v, float& hi, float& lo) {
   lo = (float)(v - (double)hi);
 }
 
-__device__ void view_params(const BcViewIn& in, BcViewParams& vp) {
+__device__ void view_params(const BcViewIn& in, BcViewParams& vp, int tile_shift) {
 #pragma clang fp contract(off)
   // (ordered so that few matrices are live at once: one thread computes this,
   // and the 4x4 inverse then fits in registers)
@@ -102,8 +102,9 @@ __device__ void view_params(const BcViewIn& in, BcViewParams& vp) {
   vp.kind = persp ? 0 : 1;
   vp.width = in.width;
   vp.height = in.height;
-  vp.tiles_x = (in.width + BC_TILE - 1) / BC_TILE;
-  vp.tiles_y = (in.height + BC_TILE - 1) / BC_TILE;
+  vp.tile_shift = tile_shift;
+  vp.tiles_x = (in.width + (1 << tile_shift) - 1) >> tile_shift;
+  vp.tiles_y = (in.height + (64 >> tile_shift) - 1) >> (6 - tile_shift);
   split(in.step, vp.dt_hi, vp.dt_lo);
   split(1.0 / in.step, vp.idt_hi, vp.idt_lo);
   split(1.0 / (double)in.width, vp.iw_hi, vp.iw_lo);
@@ -207,10 +208,11 @@ __device__ void brick_rect(const BcViewParams& vp, const BcBrick& b, int32_t* r)
       return;
     }
   }
-  r[0] = x0 / BC_TILE;
-  r[1] = y0 / BC_TILE;
-  r[2] = x1 / BC_TILE + 1;
-  r[3] = y1 / BC_TILE + 1;
+  const int sx = vp.tile_shift, sy = 6 - vp.tile_shift;
+  r[0] = x0 >> sx;
+  r[1] = y0 >> sy;
+  r[2] = (x1 >> sx) + 1;
+  r[3] = (y1 >> sy) + 1;
 }
 
 __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   // a conditional pass without the fall-back flag has no work: only its
   // (empty) work list below is written
   const bool skip = f.fin->conditional && !f.ctr->fallback;
-  if (tid < nv && !skip) view_params(f.fin->views[tid], f.views[tid]);
+  if (tid < nv && !skip) view_params(f.fin->views[tid], f.views[tid], f.tile_shift);
   __syncthreads();
   int np2 = 1;
   while (np2 < nb) np2 <<= 1;
@@ -376,11 +378,12 @@ __global__ __launch_bounds__(1024) void composite_kernel(BcFramePtrs f, float4* 
     __syncthreads();
   }
   const int tx = bx0 + (wave % kCompBlock), ty = by0 + (wave / kCompBlock);
-  const int tiles_x = (W + BC_TILE - 1) / BC_TILE, tiles_y = (H + BC_TILE - 1) / BC_TILE;
+  const int tsh = f.tile_shift, tw = 1 << tsh, th = 64 >> tsh;
+  const int tiles_x = (W + tw - 1) >> tsh, tiles_y = (H + th - 1) >> (6 - tsh);
   if (tx >= tiles_x || ty >= tiles_y) return;
   if (tx % ts != tox || ty % ts != toy) return;
-  const int px = tx * BC_TILE + (lane & (BC_TILE - 1));
-  const int py = ty * BC_TILE + (lane / BC_TILE);
+  const int px = tx * tw + (lane & (tw - 1));
+  const int py = ty * th + (lane >> tsh);
   float4 F = make_float4(0.f, 0.f, 0.f, 0.f);
   float M = -INFINITY;
   const int n = n_list;
@@ -456,7 +459,8 @@ __global__ __launch_bounds__(1024) void psnr_kernel(BcFramePtrs f, const float4*
   __shared__ int nred[1024];
   const int ts = f.fin->tile_stride, tox = f.fin->tile_ox, toy = f.fin->tile_oy;
   const int W = f.width, H = f.height, nv = f.n_views;
-  const int tiles_x = (W + BC_TILE - 1) / BC_TILE, tiles_y = (H + BC_TILE - 1) / BC_TILE;
+  const int tsh = f.tile_shift, tw = 1 << tsh, th = 64 >> tsh;
+  const int tiles_x = (W + tw - 1) >> tsh, tiles_y = (H + th - 1) >> (6 - tsh);
   const int sx = sel_count(0, tiles_x, ts, tox), sy = sel_count(0, tiles_y, ts, toy);
   const int fx = sel_first(0, ts, tox), fy = sel_first(0, ts, toy);
   const int64_t total = (int64_t)nv * sx * sy * 64;
@@ -468,7 +472,7 @@ __global__ __launch_bounds__(1024) void psnr_kernel(BcFramePtrs f, const float4*
     const int v = (int)(t / ((int64_t)sx * sy));
     const int rem = (int)(t % ((int64_t)sx * sy));
     const int tx = fx + (rem % sx) * ts, ty = fy + (rem / sx) * ts;
-    const int px = tx * BC_TILE + (lane & (BC_TILE - 1)), py = ty * BC_TILE + (lane / BC_TILE);
+    const int px = tx * tw + (lane & (tw - 1)), py = ty * th + (lane >> tsh);
     if (px >= W || py >= H) continue;
     const int64_t i = ((int64_t)v * H + py) * W + px;
     const float4 a = ref[i], b = img[i];
@@ -511,7 +515,8 @@ hipError_t bc_launch_psnr(const BcFramePtrs& f, const float4* ref, const float4*
 }
 
 hipError_t bc_launch_composite(const BcFramePtrs& f, float4* out, hipStream_t st) {
-  const int tiles_x = (f.width + BC_TILE - 1) / BC_TILE, tiles_y = (f.height + BC_TILE - 1) / BC_TILE;
+  const int tsh = f.tile_shift;
+  const int tiles_x = (f.width + (1 << tsh) - 1) >> tsh, tiles_y = (f.height + (64 >> tsh) - 1) >> (6 - tsh);
   dim3 grid((tiles_x + kCompBlock - 1) / kCompBlock, (tiles_y + kCompBlock - 1) / kCompBlock, f.n_views);
   composite_kernel<<<grid, 1024, 0, st>>>(f, out);
   return hipGetLastError();

@@ -48,6 +48,7 @@ struct BcFramePtrs {
   int32_t width, height;  // frame size (all views share it)
   int32_t urgent;         // 1: the ray caster's waves raise their issue priority (a pass that
                           // runs beside another and holds up the frame)
+  int32_t tile_shift;     // screen tiles are (1 << tile_shift) x (64 >> tile_shift) pixels
 };
 
 hipError_t bc_launch_setup(const BcFramePtrs& f, hipStream_t st);

@@ -432,9 +432,10 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
     const int cx = sel_count(r[0], r[2], ts, tox);
     const int local = (int)(item - (uint32_t)f.item_perm[lo]);
     const int tx = sel_first(r[0], ts, tox) + (local % cx) * ts, ty = sel_first(r[1], ts, toy) + (local / cx) * ts;
-    const int px = tx * BC_TILE + (lane & (BC_TILE - 1));
-    const int py = ty * BC_TILE + (lane / BC_TILE);
     const BcViewParams& vp = f.views[v];
+    const int tsh = f.tile_shift;
+    const int px = (tx << tsh) + (lane & ((1 << tsh) - 1));
+    const int py = ty * (64 >> tsh) + (lane >> tsh);
     const BcBrick& br = f.bricks[b];
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     float mx = -INFINITY;

@@ -6,7 +6,8 @@
 #define BC_MAX_VIEWS 4
 #define BC_MAX_BRICKS 4096
 #define BC_MAX_K 4096
-#define BC_TILE 8          // screen tile edge (pixels): one wave of 64 rays per work item
+#define BC_TILE 8          // default screen tile edge (pixels): one wave of 64 rays per work item;
+                           // tiles may also be 16 x 4 or 4 x 16 (always 64 pixels)
 #define BC_MB 4            // micro-block edge (voxels)
 // A 4 x 4 x 4 micro-block is stored as 16 rows (y, z) of 5 elements: voxels
 // x = 0..3 of the row and, fifth, the first voxel of the next micro-block along
@@ -48,7 +49,7 @@ struct BcFrameIn {
 struct BcViewParams {
   int32_t kind;              // 0 perspective, 1 orthographic
   int32_t width, height, tiles_x, tiles_y;
-  int32_t pad0;
+  int32_t tile_shift;        // log2 of the screen tile width: tiles are (1 << s) x (64 >> s) pixels
   float dt_hi, dt_lo;        // step (double-float)
   float idt_hi, idt_lo;      // 1 / step
   float iw_hi, iw_lo;        // 1 / width

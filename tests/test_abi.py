@@ -208,10 +208,11 @@ def test_get_bricks_after_plan(lib, host_ctx):
 
 def test_options_learned_mode_and_upsampler_argument_checks(lib, host_ctx):
     ok = {binding.BC_OPT_EMPTY_SKIP: (0, 1), binding.BC_OPT_SAMPLE_CHUNK: (32, 64),
-          binding.BC_OPT_RENDER_WORKGROUPS: (1, 4096), binding.BC_OPT_XCD_QUEUES: (0, 1)}
+          binding.BC_OPT_RENDER_WORKGROUPS: (1, 4096), binding.BC_OPT_XCD_QUEUES: (0, 1),
+          binding.BC_OPT_TILE_WIDTH: (16, 4, 8)}
     bad = {binding.BC_OPT_EMPTY_SKIP: (2, -1), binding.BC_OPT_SAMPLE_CHUNK: (16, 0),
            binding.BC_OPT_RENDER_WORKGROUPS: (0, 1 << 21), binding.BC_OPT_XCD_QUEUES: (2,),
-           binding.BC_OPT_GRAPH: (5,), 99: (1,)}
+           binding.BC_OPT_GRAPH: (5,), binding.BC_OPT_TILE_WIDTH: (2, 32, 0), 99: (1,)}
     for opt, vals in ok.items():
         for v in vals:
             assert lib.bc_set_option(host_ctx, opt, v) == binding.BC_OK, (opt, v)

@@ -266,32 +266,36 @@ def test_graph_frames_match_eager_frames(small_cube):
 
 def test_autotune_keeps_the_image(small_cube):
     """The launch shape changes only FP32 rounding inside a sample chunk (the
-    chunk size sets the base the in-chunk positions are measured from)."""
+    chunk size sets the base the in-chunk positions are measured from); the
+    screen tile shape changes nothing."""
     vol = small_cube
     rgba, vmin, vmax = _ramp(vol)
     v = synth.orbit_view(vol.shape[::-1], 11, kind="persp", width=128, height=96)
     img, bc = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax, keep=True)
-    chunk, wgs = bc.autotune(frames=2)
-    assert chunk in (32, 64) and wgs > 0
+    chunk, wgs, tile_w = bc.autotune(frames=2)
+    assert chunk in (32, 64) and wgs > 0 and tile_w in (4, 8, 16)
     again = bc.render().cpu().numpy()
     assert np.abs(again - img).max() <= 1e-6
     bc.close()
 
 
 def test_xcd_queues_and_chunks_do_not_change_the_image(small_cube):
-    """Work queues and workgroup counts only reorder independent work items:
-    bit-identical.  The chunk size changes FP32 rounding inside a chunk only."""
+    """Work queues, workgroup counts and the screen tile shape (8x8, 16x4,
+    4x16; the 90-pixel-high frame leaves partial tiles) only regroup
+    independent rays: bit-identical.  The chunk size changes FP32 rounding
+    inside a chunk only."""
     vol = small_cube
     rgba, vmin, vmax = _ramp(vol)
     views = [synth.orbit_view(vol.shape[::-1], f, kind="persp", width=120, height=90) for f in (2, 40)]
     ref = {ch: gpu_render(vol, (40, 48, 56), views, rgba, vmin, vmax,
                           options={binding.BC_OPT_XCD_QUEUES: 0, binding.BC_OPT_SAMPLE_CHUNK: ch})
            for ch in (32, 64)}
-    for q, ch, wg in ((1, 64, 64), (1, 32, 3), (0, 64, 1000), (1, 32, 2000)):
+    for q, ch, wg, tw in ((1, 64, 64, 8), (1, 32, 3, 16), (0, 64, 1000, 4), (1, 32, 2000, 8), (1, 32, 1024, 4),
+                          (0, 64, 512, 16)):
         img = gpu_render(vol, (40, 48, 56), views, rgba, vmin, vmax,
                          options={binding.BC_OPT_XCD_QUEUES: q, binding.BC_OPT_SAMPLE_CHUNK: ch,
-                                  binding.BC_OPT_RENDER_WORKGROUPS: wg})
-        assert np.array_equal(img, ref[ch]), (q, ch, wg)
+                                  binding.BC_OPT_RENDER_WORKGROUPS: wg, binding.BC_OPT_TILE_WIDTH: tw})
+        assert np.array_equal(img, ref[ch]), (q, ch, wg, tw)
     assert np.abs(ref[32] - ref[64]).max() <= 1e-6
     tf = rc.TransferFunction(rgba, vmin, vmax)
     stored = rc.store_bricks(vol, rc.brick_grid(vol.shape[::-1], (40, 48, 56)))
