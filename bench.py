@@ -72,13 +72,19 @@ ORBIT = 64
 # [options]` (the 64-frame orbit, twice).  Valid only for the kernel sources
 # whose SHA-256 is recorded; any other source reports null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "1ee4487f01ff05fdea0cfb12d7142fb3f6a0f4e9ede1eeaf0cdfbaf91e2c9997",
+    "sources_sha256": "45654b68789671c5cbb125248f64dc4c2f892125cdef4398255e0c584f5a578f",
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
-        "cube1024_persp1920x1080/f32/composite/fixed": 2356701632,
+        "cube1024_persp1920x1080/f32/composite/fixed": 2357222416,
+        "cube1024_persp1920x1080/f16/composite/fixed": 1482282308,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 999236608,
+        "cube1024_persp1920x1080/f32/mip/voxel": 2474205603,
     },
     # L2 (TCC) hit rate over the same launches: TCC_HIT / (TCC_HIT + TCC_MISS)
     "l2_hit_rate": {
-        "cube1024_persp1920x1080/f32/composite/fixed": 0.7765,
+        "cube1024_persp1920x1080/f32/composite/fixed": 0.7756,
+        "cube1024_persp1920x1080/f16/composite/fixed": 0.8035,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 0.8204,
+        "cube1024_persp1920x1080/f32/mip/voxel": 0.7190,
     },
 }
 KERNEL_SOURCES = ("bc_render.hip", "bc_types.h", "bc_kernels.h", "bc_df.h", "bc_e4m3.h")
@@ -382,7 +388,9 @@ def storage_leg(storage, args, recipe, brick, W, H, sets, vol, rgba, vmin, vmax,
     for i, img in plain_imgs:
         bc.set_views(sets[i])
         vs_plain.append(psnr_db(bc.render(out), img))
+    key = f"{args.workload}/{storage}/composite/fixed"
     leg = {"ms_per_frame": ms, "render_ms": stage[1], "gsamples_per_s": gsps, "speedup_vs_f32": base_ms / ms,
+           "traffic": measured_traffic(key), "l2_hit_rate": measured_traffic(key, "l2_hit_rate"),
            "psnr_vs_plain_f32_db": {"min": min(vs_plain), "mean": float(np.mean(vs_plain)),
                                     "frames": len(vs_plain)}}
     if ref is not None:

@@ -27,11 +27,8 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-__device__ __forceinline__ uint16_t bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest, ties to even (finite inputs)
-  return (uint16_t)(u >> 16);
-}
+// round to nearest, ties to even (one hardware conversion on gfx950)
+__device__ __forceinline__ uint16_t bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf16_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -43,54 +40,104 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast
 // ------------------------------------------------------------------ A operand
 // Lane (g = lane/16, r = lane%16) of an M-tile supplies row r (output pixel p)
 // and reduction indices k0 .. k0+7 with k0 = 32 ks + 8 g; k = tap*CIN + c.
-// `in` is an LDS tile, `win` pixels wide, `sin` BF16 elements per pixel; the
-// output pixel (prow, pcol) reads input pixel (prow + dy, pcol + dx) for tap
-// dy*3 + dx.
-template <int CIN>
-__device__ __forceinline__ bf16x8 load_a(const uint16_t* in, int win, int sin, int prow, int pcol, int k0) {
+// `in` is an LDS tile, WIN pixels wide, SIN BF16 elements per pixel; the
+// output pixel with input offset `pix` (its element index in the tile) reads
+// input pixel pix + dy*WIN + dx for tap dy*3 + dx.  Tile shapes are template
+// parameters, so that with the k-steps unrolled every tap offset is a
+// constant of the LDS instruction.
+template <int CIN, int WIN, int SIN>
+__device__ __forceinline__ int tap_offset(int tap) {
+  return tap < 9 ? ((tap / 3) * WIN + tap % 3) * SIN : -1;
+}
+
+// element offsets (from the output pixel's input position) of the lane's
+// reduction indices at k-step ks: for CIN >= 8 one run of 8 channels of one
+// tap, for CIN = 4 two taps of 4 channels; -1 for the zero padding past tap 8
+template <int CIN, int WIN, int SIN>
+__device__ __forceinline__ int2 lane_offsets(int g, int ks) {
   if (CIN >= 8) {
-    const int tap = k0 / CIN, c0 = k0 % CIN;
-    if (tap >= 9) return as_bf16x8(make_uint4(0, 0, 0, 0));
-    const int dy = tap / 3, dx = tap % 3;
-    return as_bf16x8(*reinterpret_cast<const uint4*>(in + ((prow + dy) * win + pcol + dx) * sin + c0));
-  } else {
-    // CIN == 4: the eight k values are two taps of four channels
-    uint2 h[2];
-    for (int q = 0; q < 2; ++q) {
-      const int tap = k0 / 4 + q;
-      if (tap < 9) {
-        const int dy = tap / 3, dx = tap % 3;
-        h[q] = *reinterpret_cast<const uint2*>(in + ((prow + dy) * win + pcol + dx) * sin);
-      } else {
-        h[q] = make_uint2(0, 0);
-      }
-    }
-    return as_bf16x8(make_uint4(h[0].x, h[0].y, h[1].x, h[1].y));
+    // CIN = 32: tap = ks, channel 8 g; CIN = 16: tap = 2 ks + g/2, channel 8 (g%2)
+    const int o = tap_offset<CIN, WIN, SIN>(ks * (32 / CIN) + (8 * g) / CIN);
+    return make_int2(o < 0 ? -1 : o + (8 * g) % CIN, -1);
   }
+  const int t0 = (ks * 32 + 8 * g) / 4;
+  return make_int2(tap_offset<CIN, WIN, SIN>(t0), tap_offset<CIN, WIN, SIN>(t0 + 1));
+}
+
+template <int CIN>
+__device__ __forceinline__ bf16x8 load_a(const uint16_t* in, int pix, int2 off) {
+  if (CIN >= 8) {
+    if (off.x < 0) return as_bf16x8(make_uint4(0, 0, 0, 0));
+    return as_bf16x8(*reinterpret_cast<const uint4*>(in + pix + off.x));
+  }
+  const uint2 h0 = off.x >= 0 ? *reinterpret_cast<const uint2*>(in + pix + off.x) : make_uint2(0, 0);
+  const uint2 h1 = off.y >= 0 ? *reinterpret_cast<const uint2*>(in + pix + off.y) : make_uint2(0, 0);
+  return as_bf16x8(make_uint4(h0.x, h0.y, h1.x, h1.y));
+}
+
+// wave-uniform buffer resource over `bytes` bytes at `base` (scalar registers)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wave_rsrc(const void* base, uint32_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  void* ub = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)bytes, 0x00020000);
 }
 
 // One convolution layer over an LDS tile: M output pixels in raster order of
-// an output tile `wout` wide; KS k-steps, NT n-tiles of packed weights `wf`.
-// epi(p, n, z) receives each accumulated output (bias not added).
-template <int CIN, int KS, int NT, typename Epi>
-__device__ __forceinline__ void conv_tile(const uint16_t* in, int win, int sin, int M, int wout,
-                                          const uint4* __restrict__ wf, Epi epi) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+// an output tile WOUT wide; KS k-steps, NT n-tiles of packed weights `wf`
+// (read through a buffer resource: one lane offset, the fragment offsets are
+// constants).  A wave takes R of its M-tiles at a time, so that every weight
+// fragment it loads feeds R matrix instructions (and R x NT accumulations are
+// in flight).  epi(p0, v) receives the accumulated outputs (bias not added)
+// of four consecutive pixels p0 .. p0+3 (those below M are valid): v[nt][i] is
+// pixel p0 + i, channel 16 nt + (lane % 16); per-pixel work is done once for
+// all the lane's channels.
+template <int CIN, int KS, int NT, int R, int WIN, int SIN, int M, int WOUT, typename Epi>
+__device__ __forceinline__ void conv_tile(const uint16_t* in, const uint4* __restrict__ wf, Epi epi) {
+  // (every kernel here runs 256-thread workgroups: 4 waves; the wave index is
+  // made explicitly uniform so that the per-tile guards below are scalar branches)
+  constexpr int nwaves = 4;
+  const int lane = threadIdx.x & 63, wave = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, r = lane & 15;
-  for (int mt = wave; mt * 16 < M; mt += nwaves) {
-    f32x4 acc[NT];
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int p = min(mt * 16 + r, M - 1);
-    const int prow = p / wout, pcol = p % wout;
-    for (int ks = 0; ks < KS; ++ks) {
-      const bf16x8 a = load_a<CIN>(in, win, sin, prow, pcol, ks * 32 + 8 * g);
-      for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma(a, as_bf16x8(wf[(ks * NT + nt) * 64 + lane]), acc[nt]);
+  constexpr int n_mt = (M + 15) / 16;
+  const __amdgpu_buffer_rsrc_t wr = wave_rsrc(wf, (uint32_t)(KS * NT * 64 * 16));
+  // the lane's tap offsets do not depend on the pixel: computed once
+  int2 off[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) off[ks] = lane_offsets<CIN, WIN, SIN>(g, ks);
+  for (int base = wave; base < n_mt; base += nwaves * R) {
+    f32x4 acc[R][NT];
+    int pix[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int p = min((base + nwaves * j) * 16 + r, M - 1);
+      pix[j] = ((p / WOUT) * WIN + p % WOUT) * SIN;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[j][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    for (int nt = 0; nt < NT; ++nt)
-      for (int i = 0; i < 4; ++i) {
-        const int pp = mt * 16 + 4 * g + i;
-        if (pp < M) epi(pp, nt * 16 + r, acc[nt][i]);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      bf16x8 a[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) a[j] = load_a<CIN>(in, pix[j], off[ks]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+        const u4 w = __builtin_amdgcn_raw_buffer_load_b128(wr, lane * 16, (ks * NT + nt) * 1024, 0);
+        const bf16x8 b = __builtin_bit_cast(bf16x8, w);
+        // (every slot is computed: a slot past the last M-tile reads clamped
+        // pixels and is not stored; a guard here would cost more than it saves)
+#pragma unroll
+        for (int j = 0; j < R; ++j) acc[j][nt] = mfma(a[j], b, acc[j][nt]);
       }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int mt = base + nwaves * j;
+      if (mt >= n_mt) break;
+      epi(mt * 16 + 4 * g, acc[j]);
+    }
   }
 }
 
@@ -142,11 +189,19 @@ __global__ __launch_bounds__(256) void infer_kernel(CnnInferArgs a) {
     xs[i * 4 + 3] = bf16_bits(v.w);
   }
   __syncthreads();
-  const float* b1 = bias + CNN_OFF_B1;
-  conv_tile<4, 2, 2>(xs, 22, 4, 400, 20, a.wf1, [&](int p, int c, float z) {
-    const int gy = oy - 2 + p / 20, gx = ox - 2 + p % 20;
-    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-    a1[p * PSTRIDE + c] = in ? bf16_bits(fmaxf(z + b1[c], 0.0f)) : (uint16_t)0;
+  const int r16 = threadIdx.x & 15;
+  const float b1a = bias[CNN_OFF_B1 + r16], b1b = bias[CNN_OFF_B1 + 16 + r16];
+  conv_tile<4, 2, 2, 4, 22, 4, 400, 20>(xs, a.wf1, [&](int p0, const f32x4* v) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = p0 + i;
+      if (p >= 400) break;
+      const int gy = oy - 2 + p / 20, gx = ox - 2 + p % 20;
+      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      uint16_t* d = a1 + p * PSTRIDE + r16;
+      d[0] = in ? bf16_bits(fmaxf(v[0][i] + b1a, 0.0f)) : (uint16_t)0;
+      d[16] = in ? bf16_bits(fmaxf(v[1][i] + b1b, 0.0f)) : (uint16_t)0;
+    }
   });
   __syncthreads();
   // FP32 input rows oy-1 .. oy+16 and columns ox-1 .. ox+16, clamped to the
@@ -155,18 +210,29 @@ __global__ __launch_bounds__(256) void infer_kernel(CnnInferArgs a) {
     const int gy = min(max(oy - 1 + i / XF, 0), H - 1), gx = min(max(ox - 1 + i % XF, 0), W - 1);
     reinterpret_cast<float4*>(xbuf)[i] = reinterpret_cast<const float4*>(x)[(int64_t)gy * W + gx];
   }
-  const float* b2 = bias + CNN_OFF_B2;
-  conv_tile<32, 9, 2>(a1, 20, PSTRIDE, 324, 18, a.wf2, [&](int p, int c, float z) {
-    const int gy = oy - 1 + p / 18, gx = ox - 1 + p % 18;
-    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-    a2[p * PSTRIDE + c] = in ? bf16_bits(fmaxf(z + b2[c], 0.0f)) : (uint16_t)0;
+  const float b2a = bias[CNN_OFF_B2 + r16], b2b = bias[CNN_OFF_B2 + 16 + r16];
+  conv_tile<32, 9, 2, 3, 20, PSTRIDE, 324, 18>(a1, a.wf2, [&](int p0, const f32x4* v) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = p0 + i;
+      if (p >= 324) break;
+      const int gy = oy - 1 + p / 18, gx = ox - 1 + p % 18;
+      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      uint16_t* d = a2 + p * PSTRIDE + r16;
+      d[0] = in ? bf16_bits(fmaxf(v[0][i] + b2a, 0.0f)) : (uint16_t)0;
+      d[16] = in ? bf16_bits(fmaxf(v[1][i] + b2b, 0.0f)) : (uint16_t)0;
+    }
   });
   __syncthreads();
   float* ot = reinterpret_cast<float*>(a1);   // [32][32] fine pixels x 4 channels
-  const float* b3 = bias + CNN_OFF_B3;
-  conv_tile<32, 9, 1>(a2, 18, PSTRIDE, 256, 16, a.wf3, [&](int p, int ch, float z) {
-    const int c = ch >> 2, dy = (ch >> 1) & 1, dx = ch & 1;
-    ot[((2 * (p / 16) + dy) * 32 + 2 * (p % 16) + dx) * 4 + c] = z + b3[ch];
+  // the lane's output channel 4c + 2dy + dx goes to fine pixel (2i + dy, 2j + dx), channel c
+  const float b3v = bias[CNN_OFF_B3 + r16];
+  const int c3 = r16 >> 2, dy3 = (r16 >> 1) & 1, dx3 = r16 & 1;
+  conv_tile<32, 9, 1, 4, 18, PSTRIDE, 256, 16>(a2, a.wf3, [&](int p0, const f32x4* v) {
+    // p0 .. p0+3 lie in one row of the 16-pixel-wide tile
+    float* d = ot + ((2 * (p0 / 16) + dy3) * 32 + 2 * (p0 % 16) + dx3) * 4 + c3;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[8 * i] = v[0][i] + b3v;
   });
   __syncthreads();
   // out = shuffled network output + bilinear x2 of x (half-pixel centres,
@@ -239,23 +305,37 @@ __global__ __launch_bounds__(256) void layer_kernel(CnnLayerArgs a) {
   stage_tile<CIN>(t, SIN, a.img ? a.img + n * plane * 4 : nullptr, a.in ? a.in + n * plane * CIN : nullptr, H, W, oy, ox);
   __syncthreads();
   float sq = 0.0f;
-  conv_tile<CIN, KS, COUT / 16>(t, 18, SIN, 256, 16, a.wf, [&](int p, int c, float z) {
-    const int gy = oy + p / 16, gx = ox + p % 16;
-    if (gy >= H || gx >= W) return;
-    const int64_t pix = n * plane + (int64_t)gy * W + gx;
-    if (MODE == 0) {
-      a.out[pix * COUT + c] = bf16_bits(fmaxf(z + a.bias[c], 0.0f));
-    } else if (MODE == 1) {
-      a.out[pix * COUT + c] = (a.mask[pix * COUT + c] & 0x7fffu) != 0 ? bf16_bits(z) : (uint16_t)0;
-    } else {
-      const float* xi = a.img + n * plane * 4;
-      const int ch = c >> 2, dy = (c >> 1) & 1, dx = c & 1;
-      const int Y = 2 * gy + dy, X = 2 * gx + dx;
-      const int64_t fi = ((int64_t)n * 4 * plane + (int64_t)Y * 2 * W + X) * 4 + ch;
-      const float o = (z + a.bias[c]) + bilinear2(xi, H, W, Y, X, ch);
-      const float d = o - a.target[fi];
-      sq += d * d;
-      a.out[pix * COUT + c] = bf16_bits(d * a.grad_scale);
+  constexpr int NT = COUT / 16;
+  const int r16 = threadIdx.x & 15;
+  float bv[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) bv[nt] = MODE == 1 ? 0.0f : a.bias[16 * nt + r16];
+  conv_tile<CIN, KS, NT, 4, 18, SIN, 256, 16>(t, a.wf, [&](int p0, const f32x4* v) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = p0 + i;
+      const int gy = oy + p / 16, gx = ox + p % 16;
+      if (gy >= H || gx >= W) continue;
+      const int64_t pix = n * plane + (int64_t)gy * W + gx;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int c = 16 * nt + r16;
+        const float z = v[nt][i];
+        if (MODE == 0) {
+          a.out[pix * COUT + c] = bf16_bits(fmaxf(z + bv[nt], 0.0f));
+        } else if (MODE == 1) {
+          a.out[pix * COUT + c] = (a.mask[pix * COUT + c] & 0x7fffu) != 0 ? bf16_bits(z) : (uint16_t)0;
+        } else {
+          const float* xi = a.img + n * plane * 4;
+          const int ch = c >> 2, dy = (c >> 1) & 1, dx = c & 1;
+          const int Y = 2 * gy + dy, X = 2 * gx + dx;
+          const int64_t fi = ((int64_t)n * 4 * plane + (int64_t)Y * 2 * W + X) * 4 + ch;
+          const float o = (z + bv[nt]) + bilinear2(xi, H, W, Y, X, ch);
+          const float d = o - a.target[fi];
+          sq += d * d;
+          a.out[pix * COUT + c] = bf16_bits(d * a.grad_scale);
+        }
+      }
     }
   });
   if (MODE == 2) {

@@ -14,7 +14,8 @@ struct BcLoadSrc {
 
 hipError_t bc_launch_init_minmax(BcCounters* ctr, int n, hipStream_t st);
 // bricks [first, first + count): max_rows bounds each brick's ghosted rows
-// (y * z extent); the encode's max_rows bounds its micro-block rows
+// (y * z extent); the encode's max_rows bounds its rows of micro-blocks along x
+// (y * z extent in micro-blocks)
 hipError_t bc_launch_minmax(const BcLoadSrc& src, const BcBrick* bricks, int first, int count, int max_rows,
                             BcCounters* ctr, hipStream_t st);
 hipError_t bc_launch_finalize(BcBrick* bricks, const BcCounters* ctr, int first, int count, int storage,
@@ -46,8 +47,9 @@ struct BcFramePtrs {
   int64_t max_items;
   int32_t storage;
   int32_t width, height;  // frame size (all views share it)
-  int32_t urgent;         // 1: the ray caster's waves raise their issue priority (a pass that
-                          // runs beside another and holds up the frame)
+  int32_t urgent;         // 1: the ray caster's waves issue at raised priority (2, and 3 while
+                          // evaluating); 0: at the base levels (0 and 1), for a pass that runs
+                          // beside a more urgent one
   int32_t tile_shift;     // screen tiles are (1 << tile_shift) x (64 >> tile_shift) pixels
 };
 

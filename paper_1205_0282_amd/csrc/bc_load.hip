@@ -111,35 +111,37 @@ __global__ void finalize_kernel(BcBrick* bricks, const BcCounters* ctr, int firs
   bricks[b].dmax = dmax;
 }
 
-// encode + layout: brick first + blockIdx.y; one thread per micro-block row
-// (5 stored elements), 32-bit index arithmetic
+// encode + layout: brick first + blockIdx.y; a workgroup fills the row of
+// micro-blocks (all x) at micro-block coordinates (y, z) = blockIdx.x, whose
+// stored elements are contiguous: consecutive threads write consecutive
+// elements, and a wave's reads fall on a dozen source rows
 template <typename T, int FMT>
 __global__ __launch_bounds__(256) void encode_kernel(SrcView s, const BcBrick* __restrict__ bricks, int first,
                                                      void* pool) {
   const BcBrick& br = bricks[first + (int)blockIdx.y];
   const int mb0 = br.mb[0], mb1 = br.mb[1];
-  const int n_rows = mb0 * mb1 * br.mb[2] * 16;
+  const int slabs = mb1 * br.mb[2];
   const int cx = br.hi[0] - br.lo[0], cy = br.hi[1] - br.lo[1], cz = br.hi[2] - br.lo[2];
   const float inv = 1.0f / br.scale, offs = br.offs;
-  for (int idx = (int)(blockIdx.x * blockDim.x + threadIdx.x); idx < n_rows; idx += (int)(gridDim.x * blockDim.x)) {
-    const int mbi = idx >> 4, row = idx & 15;
-    const int t = mbi / mb0;
-    const int mbx = mbi - t * mb0, mby = t % mb1, mbz = t / mb1;
-    // local ghosted index (0 <-> voxel lo-1); padding replicates the last ghost
-    const int ly = min(mby * 4 + (row & 3), cy + 1);
-    const int lz = min(mbz * 4 + (row >> 2), cz + 1);
-    const int64_t dst = br.offset + (int64_t)mbi * BC_MB_ELEMS + row * BC_ROW;
-#pragma unroll
-    for (int wx = 0; wx < BC_ROW; ++wx) {   // the fifth repeats the next micro-block's first voxel
+  const int n_el = mb0 * BC_MB_ELEMS;
+  for (int sl = (int)blockIdx.x; sl < slabs; sl += (int)gridDim.x) {
+    const int mby = sl % mb1, mbz = sl / mb1;
+    const int64_t base = br.offset + (int64_t)sl * n_el;
+    for (int e = (int)threadIdx.x; e < n_el; e += (int)blockDim.x) {
+      const int mbx = e / BC_MB_ELEMS, in = e - mbx * BC_MB_ELEMS;
+      const int row = in / BC_ROW, wx = in - row * BC_ROW;   // the fifth repeats the next micro-block's first voxel
+      // local ghosted index (0 <-> voxel lo-1); padding replicates the last ghost
       const int lx = min(mbx * 4 + wx, cx + 1);
+      const int ly = min(mby * 4 + (row & 3), cy + 1);
+      const int lz = min(mbz * 4 + (row >> 2), cz + 1);
       const float v = src_at<T>(s, br.lo[0] - 1 + lx, br.lo[1] - 1 + ly, br.lo[2] - 1 + lz);
       if (FMT == 0) {
-        static_cast<float*>(pool)[dst + wx] = v;
+        static_cast<float*>(pool)[base + e] = v;
       } else if (FMT == 1) {
-        static_cast<__half*>(pool)[dst + wx] = __float2half_rn(v);
+        static_cast<__half*>(pool)[base + e] = __float2half_rn(v);
       } else {
         const float xq = (v - offs) * inv;
-        static_cast<uint8_t*>(pool)[dst + wx] = bc_e4m3_encode(xq);
+        static_cast<uint8_t*>(pool)[base + e] = bc_e4m3_encode(xq);
       }
     }
   }
@@ -181,7 +183,8 @@ hipError_t bc_launch_finalize(BcBrick* bricks, const BcCounters* ctr, int first,
 hipError_t bc_launch_encode(const BcLoadSrc& src, const BcBrick* bricks, int first, int count, int64_t max_rows,
                             int storage, void* pool, hipStream_t st) {
   SrcView s = make_src(src);
-  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((max_rows + 255) / 256, 256)), (unsigned)count);
+  // one workgroup per row of micro-blocks (up to the largest brick's y * z count in micro-blocks)
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(max_rows, 65535)), (unsigned)count);
   if (src.dtype == 0) {
     if (storage == 0) encode_kernel<float, 0><<<grid, 256, 0, st>>>(s, bricks, first, pool);
     else if (storage == 1) encode_kernel<float, 1><<<grid, 256, 0, st>>>(s, bricks, first, pool);

@@ -360,9 +360,11 @@ __device__ __forceinline__ float frac32(int64_t v) { return (float)(uint32_t)v *
 // sample value per ray (-inf for a ray with no sample in the brick, -FLT_MAX
 // when all its samples fell in clear cells), stopping once it reaches the
 // largest value the brick stores.
-// URGENT: the waves raise their issue priority (a pass that runs beside
-// another and holds up the frame); a template parameter so that the other
-// instantiations are compiled as if it did not exist.
+// URGENT: the waves issue at the raised priority levels (2, and 3 while they
+// evaluate occupied samples) instead of the base levels (0 and 1): the plain
+// passes' setting, while a pass that runs beside a more urgent one (a learned
+// frame's coarse pass beside its validation pass) keeps the base levels; a
+// template parameter so that each instantiation holds one setting.
 template <int FMT, bool TF_LDS, int CHUNK, int OP, bool URGENT>
 __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   // table entry k at 2k, its difference to entry k+1 at 2k+1
