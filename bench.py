@@ -78,6 +78,7 @@ MEASURED_TRAFFIC = {
         "cube1024_persp1920x1080/f16/composite/fixed": 1482282308,
         "cube1024_persp1920x1080/fp8/composite/fixed": 999236608,
         "cube1024_persp1920x1080/f32/mip/voxel": 2474205603,
+        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 52067546104,
     },
     # L2 (TCC) hit rate over the same launches: TCC_HIT / (TCC_HIT + TCC_MISS)
     "l2_hit_rate": {
@@ -85,6 +86,7 @@ MEASURED_TRAFFIC = {
         "cube1024_persp1920x1080/f16/composite/fixed": 0.8035,
         "cube1024_persp1920x1080/fp8/composite/fixed": 0.8204,
         "cube1024_persp1920x1080/f32/mip/voxel": 0.7190,
+        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 0.6763,
     },
 }
 KERNEL_SOURCES = ("bc_render.hip", "bc_types.h", "bc_kernels.h", "bc_df.h", "bc_e4m3.h")
