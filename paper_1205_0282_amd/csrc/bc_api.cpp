@@ -98,6 +98,7 @@ struct bc_ctx {
   void* dev[4] = {nullptr, nullptr, nullptr, nullptr};
   // per-frame input ring (pinned host memory, kPasses pass inputs per slot) and events
   BcFrameIn* pinned[2] = {nullptr, nullptr};
+  const BcFrameIn* pinned_dev[2] = {nullptr, nullptr};   // the same buffers' device-side addresses
   hipEvent_t copy_done[2] = {nullptr, nullptr};
   bool copy_pending[2] = {false, false};
   int ring = 0;
@@ -369,6 +370,7 @@ void fill_pass(bc_ctx* c, BcFrameIn* fin, const PassSpec& p) {
 
 BcFramePtrs pass_ptrs(bc_ctx* c, BcFramePtrs f, int pass, int width, int height) {
   f.fin = reinterpret_cast<const BcFrameIn*>(static_cast<char*>(c->dev[1]) + c->off_fin + sizeof(BcFrameIn) * pass);
+  if (f.fin_src) f.fin_src += pass;
   f.width = width;
   f.height = height;
   return f;
@@ -462,8 +464,13 @@ int bc_create(int hip_device, bc_ctx** out) {
     c->render_workgroups = c->n_cu * 4;
     bool ok = true;
     for (int i = 0; i < 2 && ok; ++i) {
-      ok = hipHostMalloc(reinterpret_cast<void**>(&c->pinned[i]), sizeof(BcFrameIn) * kPasses, hipHostMallocDefault) ==
+      // host-coherent: the set-up kernel reads the pass inputs from here, and
+      // no GPU cache may serve it an earlier frame's copy of a slot
+      ok = hipHostMalloc(reinterpret_cast<void**>(&c->pinned[i]), sizeof(BcFrameIn) * kPasses, hipHostMallocCoherent) ==
            hipSuccess;
+      void* dp = nullptr;
+      ok = ok && hipHostGetDevicePointer(&dp, c->pinned[i], 0) == hipSuccess;
+      c->pinned_dev[i] = static_cast<const BcFrameIn*>(dp);
       ok = ok && hipEventCreateWithFlags(&c->copy_done[i], hipEventDisableTiming) == hipSuccess;
     }
     ok = ok && hipEventCreateWithFlags(&c->frame_done, hipEventDisableTiming) == hipSuccess;
@@ -929,15 +936,16 @@ int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_ca
   BcFramePtrs f = frame_ptrs(c);
   f.sub = sub;
   f.max_items = sub_cap;
+  // each pass's set-up kernel copies that pass's inputs from the slot
+  f.fin_src = c->pinned_dev[slot];
+  f.fin_bytes = (int32_t)fin_bytes;
   if (classify) {
     HIPCHECK(c, hipMemcpyAsync(meta + c->off_fin, pins, fin_bytes, hipMemcpyHostToDevice, st));
     HIPCHECK(c, bc_launch_classify(f, c->max_occ_words, st));
   }
-  // the frame: upload of the pass inputs, then the kernels of every pass
+  // the frame: the kernels of every pass (each pass's set-up kernel first
+  // copies the pass inputs from the pinned slot)
   auto enqueue = [&](hipStream_t s, hipEvent_t* e) -> int {
-    for (int ps = 0; ps < passes; ++ps)
-      HIPCHECK(c, hipMemcpyAsync(meta + c->off_fin + sizeof(BcFrameIn) * ps, pins + ps, fin_bytes,
-                                 hipMemcpyHostToDevice, s));
     if (e) HIPCHECK(c, hipEventRecord(e[0], s));
     if (!c->learned) {
       HIPCHECK(c, bc_launch_setup(f, s));

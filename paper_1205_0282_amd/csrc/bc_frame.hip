@@ -222,6 +222,15 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   const int tid = threadIdx.x;
   const int nv = f.n_views;
   const int nb = f.n_bricks;
+  // the pass inputs, read straight from the host's pinned buffer (two words
+  // per thread for a 256-entry table) instead of a separate copy ahead of the
+  // kernel; no thread has read `fin` before the barrier
+  if (f.fin_src) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(f.fin_src);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(const_cast<BcFrameIn*>(f.fin));
+    for (int i = tid; i < f.fin_bytes / 4; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+  }
   // a conditional pass without the fall-back flag has no work: only its
   // (empty) work list below is written
   const bool skip = f.fin->conditional && !f.ctr->fallback;

@@ -51,6 +51,10 @@ struct BcFramePtrs {
                           // evaluating); 0: at the base levels (0 and 1), for a pass that runs
                           // beside a more urgent one
   int32_t tile_shift;     // screen tiles are (1 << tile_shift) x (64 >> tile_shift) pixels
+  // the pass inputs in host-coherent pinned memory, which the set-up kernel
+  // copies to `fin` before it reads them (nullptr: `fin` already holds them)
+  const BcFrameIn* fin_src;
+  int32_t fin_bytes;      // bytes of the pass inputs to copy (a multiple of 4)
 };
 
 hipError_t bc_launch_setup(const BcFramePtrs& f, hipStream_t st);
