@@ -272,17 +272,22 @@ int bc_autotune(bc_ctx* ctx, float* out, void* stream, int frames, int64_t chose
  * stream.  bc_enable_timing(ctx, 1) waits for the last frame and opens a new
  * measurement window; each following bc_render_frame (at most 4096 of them)
  * records an event before the set-up kernel, before the ray-casting kernel,
- * before the compositing kernel and after it.  bc_enable_timing(ctx, 0) stops
- * recording.  bc_get_timing waits for the last frame and writes the summed
- * milliseconds of the window's frames per stage: ms_out[0] set-up, ms_out[1]
- * ray casting, ms_out[2] compositing; *n_frames (may be NULL) receives the
- * number of frames summed.  Errors: BC_E_STATE on a host-only context,
- * BC_E_ARG for a null ms_out. */
+ * before the compositing kernel and after it.  bc_enable_timing(ctx, 2) does
+ * the same with only the two events around the ray-casting kernel (each
+ * event recorded between dependent kernels costs the frame a few
+ * microseconds); set-up and compositing then read zero.
+ * bc_enable_timing(ctx, 0) stops recording.  bc_get_timing waits for the last
+ * frame and writes the summed milliseconds of the window's frames per stage:
+ * ms_out[0] set-up, ms_out[1] ray casting, ms_out[2] compositing; *n_frames
+ * (may be NULL) receives the number of frames summed.  Errors: BC_E_STATE on
+ * a host-only context, BC_E_ARG for a null ms_out or an enable outside
+ * {0, 1, 2}. */
 int bc_enable_timing(bc_ctx* ctx, int enable);
 int bc_get_timing(bc_ctx* ctx, double ms_out[3], int* n_frames);
 /* Whole-frame milliseconds (first event to last) of each frame of the current
- * timing window, in order, at most cap of them; *n_frames (may be NULL)
- * receives the window's frame count.  Waits for the last frame. */
+ * timing window, in order, at most cap of them (the ray-casting kernel's
+ * under bc_enable_timing(ctx, 2)); *n_frames (may be NULL) receives the
+ * window's frame count.  Waits for the last frame. */
 int bc_get_frame_times(bc_ctx* ctx, double* ms, int cap, int* n_frames);
 
 /* Brick table after bc_load_bricks: per brick the core box lo/hi (6 int32,

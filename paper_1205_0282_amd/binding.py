@@ -248,8 +248,11 @@ class BrickCaster:
     def set_option(self, option, value):
         self._check(self.lib.bc_set_option(self.h, int(option), int(value)))
 
-    def enable_timing(self, on=True):
-        self._check(self.lib.bc_enable_timing(self.h, 1 if on else 0))
+    def enable_timing(self, on=True, stages=True):
+        """Opens a timing window: events around every stage (stages=True) or
+        only around the ray-casting kernel (stages=False, fewer events
+        between the frame's kernels); on=False closes it."""
+        self._check(self.lib.bc_enable_timing(self.h, 0 if not on else (1 if stages else 2)))
 
     def timing(self):
         """(summed ms of set-up, ray casting, compositing; frames) since

@@ -154,6 +154,7 @@ struct bc_ctx {
   // per-stage timing: 4 events per frame (before setup, before render, before
   // composite, after composite) recorded on the frame's stream
   bool timing = false;
+  bool timing_stages = true;   // all four events per frame, or the two around the ray caster
   std::vector<hipEvent_t> tev;
   int timed_frames = 0;
 };
@@ -946,7 +947,7 @@ int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_ca
   // the frame: the kernels of every pass (each pass's set-up kernel first
   // copies the pass inputs from the pinned slot)
   auto enqueue = [&](hipStream_t s, hipEvent_t* e) -> int {
-    if (e) HIPCHECK(c, hipEventRecord(e[0], s));
+    if (e && c->timing_stages) HIPCHECK(c, hipEventRecord(e[0], s));
     if (!c->learned) {
       HIPCHECK(c, bc_launch_setup(f, s));
       if (e) HIPCHECK(c, hipEventRecord(e[1], s));
@@ -1004,7 +1005,7 @@ int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_ca
       HIPCHECK(c, bc_launch_render(fp, c->render_workgroups, s));
       HIPCHECK(c, bc_launch_composite(fp, reinterpret_cast<float4*>(out), s));
     }
-    if (e) HIPCHECK(c, hipEventRecord(e[3], s));
+    if (e && c->timing_stages) HIPCHECK(c, hipEventRecord(e[3], s));
     return BC_OK;
   };
   if (!c->use_graph || no_alloc) {
@@ -1052,13 +1053,13 @@ int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_ca
     }
     // with a graph only the whole frame is timed (stage slot 1)
     if (ev) {
-      HIPCHECK(c, hipEventRecord(ev[0], st));
+      if (c->timing_stages) HIPCHECK(c, hipEventRecord(ev[0], st));
       HIPCHECK(c, hipEventRecord(ev[1], st));
     }
     HIPCHECK(c, hipGraphLaunch(g.exec, st));
     if (ev) {
       HIPCHECK(c, hipEventRecord(ev[2], st));
-      HIPCHECK(c, hipEventRecord(ev[3], st));
+      if (c->timing_stages) HIPCHECK(c, hipEventRecord(ev[3], st));
     }
   }
   HIPCHECK(c, hipEventRecord(c->copy_done[slot], st));
@@ -1265,7 +1266,9 @@ int bc_enable_timing(bc_ctx* c, int enable) {
   HIPCHECK(c, hipSetDevice(c->device));
   int r = wait_frame(c);
   if (r) return r;
+  if (enable < 0 || enable > 2) return fail(c, BC_E_ARG, "bc_enable_timing: enable must be 0, 1 or 2");
   c->timing = enable != 0;
+  c->timing_stages = enable != 2;
   c->timed_frames = 0;
   return BC_OK;
 }
@@ -1282,6 +1285,7 @@ int bc_get_timing(bc_ctx* c, double ms_out[3], int* n_frames) {
   for (int k = 0; k < c->timed_frames; ++k) {
     const hipEvent_t* ev = &c->tev[4 * (size_t)k];
     for (int s = 0; s < 3; ++s) {
+      if (!c->timing_stages && s != 1) continue;
       float ms = 0.0f;
       HIPCHECK(c, hipEventElapsedTime(&ms, ev[s], ev[s + 1]));
       acc[s] += ms;
@@ -1303,7 +1307,8 @@ int bc_get_frame_times(bc_ctx* c, double* ms, int cap, int* n_frames) {
   const int n = std::min(cap, c->timed_frames);
   for (int k = 0; k < n; ++k) {
     float t = 0.0f;
-    HIPCHECK(c, hipEventElapsedTime(&t, c->tev[4 * (size_t)k], c->tev[4 * (size_t)k + 3]));
+    const size_t e0 = 4 * (size_t)k + (c->timing_stages ? 0 : 1), e1 = 4 * (size_t)k + (c->timing_stages ? 3 : 2);
+    HIPCHECK(c, hipEventElapsedTime(&t, c->tev[e0], c->tev[e1]));
     ms[k] = t;
   }
   if (n_frames) *n_frames = c->timed_frames;

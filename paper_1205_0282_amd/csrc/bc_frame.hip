@@ -215,6 +215,11 @@ __device__ void brick_rect(const BcViewParams& vp, const BcBrick& b, int32_t* r)
   r[3] = (y1 >> sy) + 1;
 }
 
+// brick counts up to which the visibility order is a rank count rather than
+// a bitonic network (nb^2 / 1024 comparisons per thread against log^2 nb
+// barriers)
+constexpr int kRankSortMax = 256;
+
 __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   __shared__ double skey[BC_MAX_BRICKS];
   __shared__ int32_t sidx[BC_MAX_BRICKS];
@@ -250,22 +255,39 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
       }
     }
     __syncthreads();
-    for (int k = 2; k <= np2; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = tid; i < np2; i += blockDim.x) {
-          const int ixj = i ^ j;
-          if (ixj > i) {
-            const bool up = (i & k) == 0;
-            const double ka = skey[i], kb = skey[ixj];
-            const int ia = sidx[i], ib = sidx[ixj];
-            const bool gt = (ka > kb) || (ka == kb && ia > ib);
-            if (gt == up) {
-              skey[i] = kb; skey[ixj] = ka;
-              sidx[i] = ib; sidx[ixj] = ia;
+    if (nb <= kRankSortMax) {
+      // few bricks: each thread counts the (key, index) pairs below its own
+      // (one pass, one barrier; the same order as the network below)
+      int rank = 0;
+      double k = 0.0;
+      if (tid < nb) {
+        k = skey[tid];
+        for (int j = 0; j < nb; ++j) {
+          const double kj = skey[j];
+          rank += (kj < k || (kj == k && j < tid)) ? 1 : 0;
+        }
+      }
+      __syncthreads();
+      if (tid < nb) sidx[rank] = tid;
+      __syncthreads();
+    } else {
+      for (int k = 2; k <= np2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int i = tid; i < np2; i += blockDim.x) {
+            const int ixj = i ^ j;
+            if (ixj > i) {
+              const bool up = (i & k) == 0;
+              const double ka = skey[i], kb = skey[ixj];
+              const int ia = sidx[i], ib = sidx[ixj];
+              const bool gt = (ka > kb) || (ka == kb && ia > ib);
+              if (gt == up) {
+                skey[i] = kb; skey[ixj] = ka;
+                sidx[i] = ib; sidx[ixj] = ia;
+              }
             }
           }
+          __syncthreads();
         }
-        __syncthreads();
       }
     }
     for (int i = tid; i < nb; i += blockDim.x) f.order[v * nb + i] = sidx[i];
@@ -457,6 +479,95 @@ __global__ __launch_bounds__(1024) void composite_kernel(BcFramePtrs f, float4* 
   if (px < W && py < H) out[((int64_t)v * H + py) * W + px] = F;
 }
 
+// Few bricks (up to kTileCompMax): one wave per screen tile, four per
+// workgroup (a 2x2 block of tiles), no culling pass and no barrier.  Lane j
+// takes entries j, j + 64, ... of the view's visibility order and finds the
+// brick's sub-image tile for this screen tile (its rectangle, and the brick's
+// first work item, loaded together); the wave then folds the covering tiles
+// in visibility order, four sub-image loads in flight.  Entries that do not
+// cover the tile fold as zero in composite_kernel, which changes no bit, so
+// the two kernels' images are identical.
+constexpr int kTileCompMax = 128;
+__global__ __launch_bounds__(256) void composite_tile_kernel(BcFramePtrs f, float4* __restrict__ out) {
+  if (f.fin->conditional && !f.ctr->fallback) return;
+  const int v = blockIdx.z;
+  const int nb = f.n_bricks, nv = f.n_views;
+  const int W = f.width, H = f.height;
+  const int ts = f.fin->tile_stride, tox = f.fin->tile_ox, toy = f.fin->tile_oy;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tx = (int)blockIdx.x * 2 + (wave & 1), ty = (int)blockIdx.y * 2 + (wave >> 1);
+  const int tsh = f.tile_shift, tw = 1 << tsh, th = 64 >> tsh;
+  const int tiles_x = (W + tw - 1) >> tsh, tiles_y = (H + th - 1) >> (6 - tsh);
+  if (tx >= tiles_x || ty >= tiles_y) return;
+  if (tx % ts != tox || ty % ts != toy) return;
+  const int px = tx * tw + (lane & (tw - 1));
+  const int py = ty * th + (lane >> tsh);
+  float4 F = make_float4(0.f, 0.f, 0.f, 0.f);
+  float M = -INFINITY;
+  for (int base = 0; base < nb; base += 64) {
+    const int k = base + lane;
+    int my_item = -1;
+    if (k < nb) {
+      const int b = f.order[v * nb + k];
+      const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
+      const int r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+      const int64_t first = f.item_base[b * nv + v];
+      if (tx >= r0 && tx < r2 && ty >= r1 && ty < r3) {
+        const int fx = sel_first(r0, ts, tox), fy = sel_first(r1, ts, toy);
+        const int cx = sel_count(r0, r2, ts, tox);
+        const int64_t item = first + (int64_t)((ty - fy) / ts) * cx + (tx - fx) / ts;
+        if (item < (int64_t)f.max_items) my_item = (int)item;
+      }
+    }
+    uint64_t cover = __ballot(my_item >= 0);
+    while (cover) {
+      int it[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        it[u] = -1;
+        if (cover) {
+          const int j = __builtin_ctzll(cover);
+          cover &= cover - 1ull;
+          it[u] = __shfl(my_item, j);
+        }
+      }
+      if (f.op == 1) {
+        const float* subf = reinterpret_cast<const float*>(f.sub);
+        float m4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m4[u] = it[u] >= 0 ? subf[(int64_t)it[u] * 64 + lane] : -INFINITY;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) M = fmaxf(M, m4[u]);
+        continue;
+      }
+      float4 S[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        S[u] = it[u] >= 0 ? f.sub[(int64_t)it[u] * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float om = 1.0f - F.w;
+        F.x = __builtin_fmaf(om, S[u].x, F.x);
+        F.y = __builtin_fmaf(om, S[u].y, F.y);
+        F.z = __builtin_fmaf(om, S[u].z, F.z);
+        F.w = __builtin_fmaf(om, S[u].w, F.w);
+      }
+    }
+  }
+  if (f.op == 1 && M != -INFINITY) {
+    const int K = f.fin->K;
+    const float4* tab = reinterpret_cast<const float4*>(f.fin->table);
+    float x = __builtin_fmaf(M, f.fin->tf_scale, f.fin->tf_bias);
+    x = fminf(fmaxf(x, 0.0f), (float)(K - 1));
+    const int i = min((int)x, K - 2);
+    const float t = x - (float)i;
+    const float4 a = tab[i], b = tab[i + 1];
+    F = make_float4(__builtin_fmaf(t, b.x - a.x, a.x), __builtin_fmaf(t, b.y - a.y, a.y),
+                    __builtin_fmaf(t, b.z - a.z, a.z), __builtin_fmaf(t, b.w - a.w, a.w));
+  }
+  if (px < W && py < H) out[((int64_t)v * H + py) * W + px] = F;
+}
+
 // Learned frame: PSNR (peak 1) of the upsampled image against the plain
 // render over the validation tiles, and the fall-back decision.
 __global__ __launch_bounds__(1024) void psnr_kernel(BcFramePtrs f, const float4* __restrict__ ref,
@@ -526,7 +637,12 @@ hipError_t bc_launch_psnr(const BcFramePtrs& f, const float4* ref, const float4*
 hipError_t bc_launch_composite(const BcFramePtrs& f, float4* out, hipStream_t st) {
   const int tsh = f.tile_shift;
   const int tiles_x = (f.width + (1 << tsh) - 1) >> tsh, tiles_y = (f.height + (64 >> tsh) - 1) >> (6 - tsh);
-  dim3 grid((tiles_x + kCompBlock - 1) / kCompBlock, (tiles_y + kCompBlock - 1) / kCompBlock, f.n_views);
-  composite_kernel<<<grid, 1024, 0, st>>>(f, out);
+  if (f.n_bricks <= kTileCompMax) {
+    dim3 grid((tiles_x + 1) / 2, (tiles_y + 1) / 2, f.n_views);
+    composite_tile_kernel<<<grid, 256, 0, st>>>(f, out);
+  } else {
+    dim3 grid((tiles_x + kCompBlock - 1) / kCompBlock, (tiles_y + kCompBlock - 1) / kCompBlock, f.n_views);
+    composite_kernel<<<grid, 1024, 0, st>>>(f, out);
+  }
   return hipGetLastError();
 }

@@ -364,6 +364,29 @@ def test_more_than_64_bricks_per_block_of_tiles():
     assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
 
 
+def test_between_64_and_128_bricks():
+    """100 bricks (5x5x4 of 8x8x10 voxels over a 40^3 cube): the per-tile
+    compositing kernel (up to 128 bricks) walks the visibility order in two
+    slices of 64.  Compositing and maximum intensity projection match the
+    oracle at every pixel of a partial-tile frame."""
+    from oracle import mip
+    dims = (40, 40, 40)
+    vol = synth.make_cube(synth.CubeRecipe(dims, seed=17, n_sources=10, sigma_lo=2.0, sigma_hi=5.0), workers=4)
+    rgba, vmin, vmax = _ramp(vol)
+    v = synth.orbit_view(dims, 11, kind="persp", width=70, height=50, elevation_deg=25.0)
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (8, 8, 10)))
+    assert len(rc.brick_grid(dims, (8, 8, 10))) == 100
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    img = gpu_render(vol, (8, 8, 10), [v], rgba, vmin, vmax)
+    res = rc.render_bricked(stored, dims, cam_of(v), tf, 0.5, 0.99)
+    err, _, _ = compare(img[0].reshape(-1, 4), res, "100 bricks")
+    assert err <= TOL
+    assert res.image[:, 3].max() > 0.3
+    img = gpu_render(vol, (8, 8, 10), [v], rgba, vmin, vmax, op=("mip", "fixed"))
+    res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, 0.5)
+    assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
+
+
 @pytest.mark.parametrize("dims,brick", [((1, 1, 1), (1, 1, 1)), ((2, 1, 3), (1, 1, 2)), ((5, 1, 1), (2, 1, 1)),
                                         ((3, 4, 1), (3, 4, 1))])
 def test_smallest_cubes_bricks_and_frames(dims, brick):
@@ -437,3 +460,36 @@ def test_constructed_exact_ties_match_an_enumerated_result():
     res = rc.render_bricked(stored, dims, cam_of(v), rc.TransferFunction(rgba, 0.0, 1.0), 1.0, tau)
     err, _, _ = compare(img[0].reshape(-1, 4), res, "transparent run at tau")
     assert err <= TOL
+
+
+def test_timing_windows(small_cube):
+    """Stage timing: every stage positive with events between all stages; with
+    only the ray caster's two events, set-up and compositing read zero and the
+    per-frame times are the ray caster's; an enable outside {0, 1, 2} is refused."""
+    import torch
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    views = [synth.orbit_view(vol.shape[::-1], f, kind="persp", width=160, height=120) for f in (3, 9, 21)]
+    img, bc = gpu_render(vol, (48, 40, 64), views[:1], rgba, vmin, vmax, keep=True)
+    out = torch.empty((1, 120, 160, 4), device="cuda")
+    for stages in (True, False):
+        bc.enable_timing(True, stages=stages)
+        for v in views:
+            bc.set_views([v])
+            bc.render(out)
+        ms, n = bc.timing()
+        ft = bc.frame_times()
+        bc.enable_timing(False)
+        assert n == len(views) and len(ft) == len(views)
+        assert ms[1] > 0
+        if stages:
+            assert ms[0] > 0 and ms[2] > 0
+            assert sum(ft) >= ms[1]
+        else:
+            assert ms[0] == 0 and ms[2] == 0
+            assert abs(sum(ft) - ms[1]) <= 1e-6 * max(ms[1], 1.0)
+    with pytest.raises(binding.BrickcastError):
+        bc._check(bc.lib.bc_enable_timing(bc.h, 3))
+    bc.set_views(views[:1])
+    assert np.array_equal(bc.render(out).cpu().numpy().astype(np.float64), img)
+    bc.close()
