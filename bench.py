@@ -72,20 +72,20 @@ ORBIT = 64
 # [options]` (the 64-frame orbit, twice).  Valid only for the kernel sources
 # whose SHA-256 is recorded; any other source reports null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "45654b68789671c5cbb125248f64dc4c2f892125cdef4398255e0c584f5a578f",
+    "sources_sha256": "96ff4ef3b2feb9f56144b22a5075bbeb1bee267f4ee1e775d5500dd357ec4d07",
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
-        "cube1024_persp1920x1080/f32/composite/fixed": 2357222416,
-        "cube1024_persp1920x1080/f16/composite/fixed": 1482282308,
-        "cube1024_persp1920x1080/fp8/composite/fixed": 999236608,
-        "cube1024_persp1920x1080/f32/mip/voxel": 2474205603,
-        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 52067546104,
+        "cube1024_persp1920x1080/f32/composite/fixed": 2362852357,
+        "cube1024_persp1920x1080/f16/composite/fixed": 1487265812,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 1002453455,
+        "cube1024_persp1920x1080/f32/mip/voxel": 2479868031,
+        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 52075343478,
     },
     # L2 (TCC) hit rate over the same launches: TCC_HIT / (TCC_HIT + TCC_MISS)
     "l2_hit_rate": {
-        "cube1024_persp1920x1080/f32/composite/fixed": 0.7756,
-        "cube1024_persp1920x1080/f16/composite/fixed": 0.8035,
-        "cube1024_persp1920x1080/fp8/composite/fixed": 0.8204,
-        "cube1024_persp1920x1080/f32/mip/voxel": 0.7190,
+        "cube1024_persp1920x1080/f32/composite/fixed": 0.7747,
+        "cube1024_persp1920x1080/f16/composite/fixed": 0.8025,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 0.8194,
+        "cube1024_persp1920x1080/f32/mip/voxel": 0.7183,
         "cube3000x3000x1500_f16_4views/f16/composite/fixed": 0.6763,
     },
 }
