@@ -235,7 +235,7 @@ int bc_get_frame_stats(bc_ctx* ctx, bc_frame_stats* stats);
  *  BC_OPT_SAMPLE_CHUNK (32 or 64, default 32): samples per ray whose
  *    occupancy is gathered before the occupied ones are evaluated.  Images do
  *    not depend on it.
- *  BC_OPT_GRAPH (default 0): 1 captures each frame's uploads and kernels once
+ *  BC_OPT_GRAPH (default 0): 1 captures each frame's kernels once
  *    into a HIP graph (one per per-frame input buffer; captured again when the
  *    view count, frame size, table size, launch options, mode or `out` change)
  *    and replays it; images are identical.  With a graph, timing reports the

@@ -1,5 +1,6 @@
 // Host runtime of the bricked ray caster: argument checking, memory planning,
-// brick loading, per-frame parameter upload and kernel sequencing.
+// brick loading, per-frame parameters (read by the set-up kernel from pinned
+// host memory) and kernel sequencing.
 // The declarations and the contract of every entry point are in
 // include/brickcast.h.
 #include <hip/hip_runtime.h>
@@ -99,8 +100,8 @@ struct bc_ctx {
   // per-frame input ring (pinned host memory, kPasses pass inputs per slot) and events
   BcFrameIn* pinned[2] = {nullptr, nullptr};
   const BcFrameIn* pinned_dev[2] = {nullptr, nullptr};   // the same buffers' device-side addresses
-  hipEvent_t copy_done[2] = {nullptr, nullptr};
-  bool copy_pending[2] = {false, false};
+  hipEvent_t slot_done[2] = {nullptr, nullptr};
+  bool slot_pending[2] = {false, false};
   int ring = 0;
   hipEvent_t frame_done = nullptr;
   bool frame_pending = false;
@@ -472,7 +473,7 @@ int bc_create(int hip_device, bc_ctx** out) {
       void* dp = nullptr;
       ok = ok && hipHostGetDevicePointer(&dp, c->pinned[i], 0) == hipSuccess;
       c->pinned_dev[i] = static_cast<const BcFrameIn*>(dp);
-      ok = ok && hipEventCreateWithFlags(&c->copy_done[i], hipEventDisableTiming) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&c->slot_done[i], hipEventDisableTiming) == hipSuccess;
     }
     ok = ok && hipEventCreateWithFlags(&c->frame_done, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) == hipSuccess;
@@ -502,7 +503,7 @@ void bc_destroy(bc_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->frame_pending) (void)hipEventSynchronize(c->frame_done);
     for (int i = 0; i < 2; ++i) {
-      if (c->copy_done[i]) (void)hipEventDestroy(c->copy_done[i]);
+      if (c->slot_done[i]) (void)hipEventDestroy(c->slot_done[i]);
       if (c->pinned[i]) (void)hipHostFree(c->pinned[i]);
     }
     if (c->frame_done) (void)hipEventDestroy(c->frame_done);
@@ -862,7 +863,7 @@ int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_ca
   HIPCHECK(c, hipSetDevice(c->device));
   const int slot = c->ring;
   c->ring ^= 1;
-  if (c->copy_pending[slot]) HIPCHECK(c, hipEventSynchronize(c->copy_done[slot]));
+  if (c->slot_pending[slot]) HIPCHECK(c, hipEventSynchronize(c->slot_done[slot]));
   BcFrameIn* pins = c->pinned[slot];
   char* meta = static_cast<char*>(c->dev[1]);
   const int passes = c->learned ? kPasses : 1;
@@ -1062,8 +1063,8 @@ int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_ca
       if (c->timing_stages) HIPCHECK(c, hipEventRecord(ev[3], st));
     }
   }
-  HIPCHECK(c, hipEventRecord(c->copy_done[slot], st));
-  c->copy_pending[slot] = true;
+  HIPCHECK(c, hipEventRecord(c->slot_done[slot], st));
+  c->slot_pending[slot] = true;
   HIPCHECK(c, hipEventRecord(c->frame_done, st));
   c->frame_pending = true;
   c->last_learned = c->learned;
