@@ -249,3 +249,48 @@ def test_operator_argument_checks(lib, host_ctx):
     for op, st in ((binding.BC_OP_MIP, binding.BC_STEP_PER_VOXEL), (binding.BC_OP_MIP, binding.BC_STEP_FIXED),
                    (binding.BC_OP_COMPOSITE, binding.BC_STEP_FIXED)):
         assert lib.bc_set_operator(host_ctx, op, st) == binding.BC_OK
+
+
+def test_header_is_c99_and_a_c_program_links(lib, tmp_path):
+    """The header compiles as strict C99 (no C++ in it), a C program links
+    against the library and plans through it on a host-only context, and the
+    C structs have the sizes the binding's ctypes structures assume."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "plan.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "brickcast.h"
+int main(void) {
+  bc_ctx* h = NULL;
+  if (bc_create(-1, &h) != BC_OK) return 1;
+  bc_volume_desc d = {0};
+  for (int a = 0; a < 3; ++a) { d.global_dims[a] = 64; d.share_hi[a] = 64; d.brick_dims[a] = 32; }
+  d.ghost = 1;
+  size_t sizes[4];
+  const int r = bc_plan(h, &d, 1, 64, 64, 0, sizes);
+  printf("%d %zu %zu %zu %zu %zu %zu %zu\n", r, sizes[0], sizes[1], sizes[2], sizes[3], sizeof(bc_view),
+         sizeof(bc_volume_desc), sizeof(bc_frame_stats));
+  bc_destroy(h);
+  return r == BC_OK ? 0 : 2;
+}
+''')
+    libdir = os.path.dirname(binding.LIB_PATH)
+    exe = tmp_path / "plan"
+    build = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                            os.path.join(ROOT, "include"), str(src), "-L", libdir, "-lbrickcast",
+                            "-Wl,-rpath," + libdir, "-o", str(exe)], capture_output=True, text=True)
+    assert build.returncode == 0, build.stderr
+    run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert run.returncode == 0, run.stdout + run.stderr
+    vals = [int(x) for x in run.stdout.split()]
+    h = C.c_void_p()
+    assert lib.bc_create(-1, C.byref(h)) == binding.BC_OK
+    code, sizes = _plan(lib, h, _desc())
+    lib.bc_destroy(h)
+    assert vals[0] == code == binding.BC_OK
+    assert vals[1:5] == sizes
+    assert vals[5:] == [C.sizeof(binding.View), C.sizeof(binding.VolumeDesc), C.sizeof(binding.FrameStats)]
