@@ -493,3 +493,35 @@ def test_timing_windows(small_cube):
     bc.set_views(views[:1])
     assert np.array_equal(bc.render(out).cpu().numpy().astype(np.float64), img)
     bc.close()
+
+
+@pytest.mark.parametrize("K,kind", [(2, "random"), (2, "ramp"), (1024, "ramp"), (1025, "ramp"), (4096, "ramp")])
+def test_table_sizes_at_the_limits(small_cube, K, kind):
+    """Tables of 2 entries (the smallest), 1024 (the largest the ray caster
+    stages in LDS), 1025 (read from device memory) and 4096 (the limit):
+    compositing and maximum intensity projection match the oracle at every
+    pixel of a partial-tile frame.  The large tables are smooth (the ramp of
+    the workloads, opacity zero below 3 so skipping stays in play): the table
+    coordinate is FP32, so the interpolated value's rounding reaches the
+    colour multiplied by (K-1)/(vmax-vmin) and by the step between
+    neighbouring entries, and a random 1024-entry table exceeds the 2e-5 bar
+    (2.8e-5 on this frame) while a smooth one stays far below it."""
+    from oracle import mip
+    vol = small_cube
+    vmin, vmax = float(vol.min()), float(vol.max())
+    if kind == "random":
+        rgba = synth.random_tf(np.random.default_rng(100 + K), K, alpha_max=0.5)
+    else:
+        rgba = synth.ramp_tf(vmin, vmax, K=K)
+    v = synth.orbit_view(vol.shape[::-1], 13, kind="persp", width=90, height=70)
+    dims = vol.shape[::-1]
+    stored = rc.store_bricks(vol, rc.brick_grid(dims, (64, 64, 64)))
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    img = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax)
+    res = rc.render_bricked(stored, dims, cam_of(v), tf, 0.5, 0.99)
+    err, _, _ = compare(img[0].reshape(-1, 4), res, f"K = {K} ({kind})")
+    assert err <= TOL
+    assert res.image[:, 3].max() > 0.05
+    img = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax, op=("mip", "fixed"))
+    res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, 0.5)
+    assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
