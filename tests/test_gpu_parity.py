@@ -525,3 +525,35 @@ def test_table_sizes_at_the_limits(small_cube, K, kind):
     img = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax, op=("mip", "fixed"))
     res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, 0.5)
     assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
+
+
+@pytest.mark.parametrize("eye,target", [((70.3, 61.7, 45.2), (20.0, 90.0, 120.0)),    # inside a brick
+                                        ((64.0, 64.0, 64.0), (128.0, 20.0, 10.0)),    # on a brick corner
+                                        ((30.5, 140.0, 64.2), (64.0, 0.0, 64.0))])    # outside, close
+def test_eye_inside_or_next_to_the_cube(small_cube, eye, target):
+    """Fly-through views: the eye inside a brick (rays start at the eye, that
+    brick's rectangle is the whole frame and its order key is negative, bricks
+    behind the eye take no samples), on the corner shared by eight bricks, and
+    just outside with a wide field of view (brick corners behind the near
+    plane).  Compositing and maximum intensity projection match the oracle at
+    every pixel, and the visibility order matches bit for bit."""
+    from oracle import mip
+    vol = small_cube
+    rgba, vmin, vmax = _ramp(vol)
+    W, H = 72, 54
+    v = synth.ViewSpec(synth.look_at(eye, target, (0.0, 1.0, 0.0)), synth.perspective(80.0, W / H, 0.1, 500.0), W, H)
+    dims = vol.shape[::-1]
+    bricks = rc.brick_grid(dims, (64, 64, 64))
+    stored = rc.store_bricks(vol, bricks)
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    img, bc = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax, keep=True)
+    cam = cam_of(v)
+    assert np.array_equal(bc.visibility_order(0), np.asarray(rc.visibility_order(bricks, cam)[0], np.int32))
+    bc.close()
+    res = rc.render_bricked(stored, dims, cam, tf, 0.5, 0.99)
+    err, _, _ = compare(img[0].reshape(-1, 4), res, f"eye {eye}")
+    assert err <= TOL
+    assert res.image[:, 3].max() > 0.05
+    img = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax, op=("mip", "fixed"))
+    res = mip.render_mip_bricked(stored, dims, cam, tf, 0.5)
+    assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
