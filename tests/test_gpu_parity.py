@@ -557,3 +557,30 @@ def test_eye_inside_or_next_to_the_cube(small_cube, eye, target):
     img = gpu_render(vol, (64, 64, 64), [v], rgba, vmin, vmax, op=("mip", "fixed"))
     res = mip.render_mip_bricked(stored, dims, cam, tf, 0.5)
     assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
+
+
+@pytest.mark.parametrize("step,brick,size", [(0.05, (20, 18, 22), (32, 24)), (3.3, (6, 6, 6), (44, 36)),
+                                             (7.9, (6, 6, 6), (44, 36))])
+def test_steps_far_below_a_voxel_and_above_a_brick(step, brick, size):
+    """Sample steps of 0.05 voxels (up to about 750 samples, two dozen chunks,
+    per ray in a brick) and of 3.3 and 7.9 voxels against 6-voxel bricks (most
+    bricks take zero or one sample of a ray, and a sample's owner brick is
+    decided far from the previous one): compositing with opacity correction
+    for the step, and maximum intensity projection, against the oracle."""
+    from oracle import mip
+    dims = (60, 54, 66)
+    vol = synth.make_cube(synth.CubeRecipe(dims, seed=41, n_sources=9, sigma_lo=2.0, sigma_hi=6.0), workers=4)
+    rgba, vmin, vmax = _ramp(vol)
+    v = synth.orbit_view(dims, 19, kind="persp", width=size[0], height=size[1], elevation_deg=-15.0, step=step,
+                         ert=0.95)
+    bricks = rc.brick_grid(dims, brick)
+    stored = rc.store_bricks(vol, bricks)
+    tf = rc.TransferFunction(rgba, vmin, vmax)
+    img = gpu_render(vol, brick, [v], rgba, vmin, vmax)
+    res = rc.render_bricked(stored, dims, cam_of(v), tf, step, 0.95)
+    err, _, _ = compare(img[0].reshape(-1, 4), res, f"step {step}")
+    assert err <= TOL
+    assert res.image[:, 3].max() > 0.05
+    img = gpu_render(vol, brick, [v], rgba, vmin, vmax, op=("mip", "fixed"))
+    res = mip.render_mip_bricked(stored, dims, cam_of(v), tf, step)
+    assert mip.max_abs_with_branches(img[0].reshape(-1, 4), res).max() <= TOL
