@@ -72,15 +72,24 @@ def test_brute_force_cubes_four_views(n, brick, kind, seed):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "fp8"])
-def test_stored_bricks_bit_exact(storage):
-    """GPU bricking, ghosts and encoders against the oracle's, element by element."""
+@pytest.mark.parametrize("src", ["f32 host", "f16 host", "f16 device"])
+def test_stored_bricks_bit_exact(storage, src):
+    """GPU bricking, ghosts and encoders against the oracle's, element by
+    element, from FP32 and FP16 sources in host or device memory (an FP16
+    source widens exactly to the FP32 values the encoders take)."""
+    import torch
     rng = np.random.default_rng(11)
     dims = (37, 29, 21)
     vol = (rng.standard_normal(dims[::-1]) * 3).astype(np.float32)
+    dtype, place = src.split()
+    if dtype == "f16":
+        vol16 = vol.astype(np.float16)
+        vol = vol16.astype(np.float32)
     bc = binding.BrickCaster(0)
-    bc.plan(dims, (16, 16, 8), storage=storage, max_w=16, max_h=16)
+    bc.plan(dims, (16, 16, 8), storage=storage, src_dtype=dtype, max_w=16, max_h=16)
     bc.bind()
-    bc.load(vol)
+    source = vol16 if dtype == "f16" else vol
+    bc.load(torch.from_numpy(source).cuda() if place == "device" else source)
     lohi, so, mm = bc.bricks()
     bricks = rc.brick_grid(dims, (16, 16, 8))
     for b in bricks:
