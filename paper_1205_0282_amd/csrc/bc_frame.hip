@@ -243,46 +243,61 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
   __syncthreads();
   int np2 = 1;
   while (np2 < nb) np2 <<= 1;
-  for (int v = 0; v < (skip ? 0 : nv); ++v) {
-    const BcViewParams& vp = f.views[v];
-    for (int i = tid; i < np2; i += blockDim.x) {
-      if (i < nb) {
-        skey[i] = brick_key(vp, f.bricks[i]);
-        sidx[i] = i;
-      } else {
-        skey[i] = DBL_MAX;
-        sidx[i] = 0x7fffffff;
+  // views whose padded key arrays fit side by side are ordered concurrently,
+  // each by its own group of threads; the groups pass the same barriers, as
+  // every view has the same brick count
+  const int groups = (nv > 1 && nv * np2 <= BC_MAX_BRICKS) ? nv : 1;
+  const int T = (int)blockDim.x / groups;
+  const int grp = min(tid / T, groups - 1), t = tid - grp * T;
+  const bool member = tid < groups * T;
+  double* gkey = skey + grp * np2;
+  int32_t* gidx = sidx + grp * np2;
+  for (int v0 = 0; v0 < (skip ? 0 : nv); v0 += groups) {
+    const int v = v0 + grp;
+    const bool on = member && v < nv;
+    const BcViewParams& vp = f.views[on ? v : v0];
+    if (on) {
+      for (int i = t; i < np2; i += T) {
+        if (i < nb) {
+          gkey[i] = brick_key(vp, f.bricks[i]);
+          gidx[i] = i;
+        } else {
+          gkey[i] = DBL_MAX;
+          gidx[i] = 0x7fffffff;
+        }
       }
     }
     __syncthreads();
     if (nb <= kRankSortMax) {
       // few bricks: each thread counts the (key, index) pairs below its own
-      // (one pass, one barrier; the same order as the network below)
+      // (one pass, one barrier; the same order as the network below); a
+      // group has at least 256 threads
       int rank = 0;
-      double k = 0.0;
-      if (tid < nb) {
-        k = skey[tid];
+      if (on && t < nb) {
+        const double k = gkey[t];
         for (int j = 0; j < nb; ++j) {
-          const double kj = skey[j];
-          rank += (kj < k || (kj == k && j < tid)) ? 1 : 0;
+          const double kj = gkey[j];
+          rank += (kj < k || (kj == k && j < t)) ? 1 : 0;
         }
       }
       __syncthreads();
-      if (tid < nb) sidx[rank] = tid;
+      if (on && t < nb) gidx[rank] = t;
       __syncthreads();
     } else {
       for (int k = 2; k <= np2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-          for (int i = tid; i < np2; i += blockDim.x) {
-            const int ixj = i ^ j;
-            if (ixj > i) {
-              const bool up = (i & k) == 0;
-              const double ka = skey[i], kb = skey[ixj];
-              const int ia = sidx[i], ib = sidx[ixj];
-              const bool gt = (ka > kb) || (ka == kb && ia > ib);
-              if (gt == up) {
-                skey[i] = kb; skey[ixj] = ka;
-                sidx[i] = ib; sidx[ixj] = ia;
+          if (on) {
+            for (int i = t; i < np2; i += T) {
+              const int ixj = i ^ j;
+              if (ixj > i) {
+                const bool up = (i & k) == 0;
+                const double ka = gkey[i], kb = gkey[ixj];
+                const int ia = gidx[i], ib = gidx[ixj];
+                const bool gt = (ka > kb) || (ka == kb && ia > ib);
+                if (gt == up) {
+                  gkey[i] = kb; gkey[ixj] = ka;
+                  gidx[i] = ib; gidx[ixj] = ia;
+                }
               }
             }
           }
@@ -290,8 +305,10 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
         }
       }
     }
-    for (int i = tid; i < nb; i += blockDim.x) f.order[v * nb + i] = sidx[i];
-    for (int b = tid; b < nb; b += blockDim.x) brick_rect(vp, f.bricks[b], f.rects + ((int64_t)v * nb + b) * 4);
+    if (on) {
+      for (int i = t; i < nb; i += T) f.order[v * nb + i] = gidx[i];
+      for (int b = t; b < nb; b += T) brick_rect(vp, f.bricks[b], f.rects + ((int64_t)v * nb + b) * 4);
+    }
     __syncthreads();
   }
   // work items: entry (b, v) owns the selected tiles of its rectangle (none in
