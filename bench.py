@@ -72,21 +72,21 @@ ORBIT = 64
 # [options]` (the 64-frame orbit, twice).  Valid only for the kernel sources
 # whose SHA-256 is recorded; any other source reports null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "96ff4ef3b2feb9f56144b22a5075bbeb1bee267f4ee1e775d5500dd357ec4d07",
+    "sources_sha256": "d332b888d98c1a05e5aa77db1e25a7f3539363712b48330435002e74754ceb37",
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
-        "cube1024_persp1920x1080/f32/composite/fixed": 2362852357,
-        "cube1024_persp1920x1080/f16/composite/fixed": 1487265812,
-        "cube1024_persp1920x1080/fp8/composite/fixed": 1002453455,
-        "cube1024_persp1920x1080/f32/mip/voxel": 2479868031,
-        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 52075343478,
+        "cube1024_persp1920x1080/f32/composite/fixed": 2297301823,
+        "cube1024_persp1920x1080/f16/composite/fixed": 1486305359,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 1001427634,
+        "cube1024_persp1920x1080/f32/mip/voxel": 2480374387,
+        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 52093890540,
     },
     # L2 (TCC) hit rate over the same launches: TCC_HIT / (TCC_HIT + TCC_MISS)
     "l2_hit_rate": {
-        "cube1024_persp1920x1080/f32/composite/fixed": 0.7747,
-        "cube1024_persp1920x1080/f16/composite/fixed": 0.8025,
-        "cube1024_persp1920x1080/fp8/composite/fixed": 0.8194,
-        "cube1024_persp1920x1080/f32/mip/voxel": 0.7183,
-        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 0.6763,
+        "cube1024_persp1920x1080/f32/composite/fixed": 0.7577,
+        "cube1024_persp1920x1080/f16/composite/fixed": 0.8027,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 0.8196,
+        "cube1024_persp1920x1080/f32/mip/voxel": 0.7181,
+        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 0.6762,
     },
 }
 KERNEL_SOURCES = ("bc_render.hip", "bc_types.h", "bc_kernels.h", "bc_df.h", "bc_e4m3.h")

@@ -27,6 +27,9 @@
 // chunk it first gathers the 32 occupancy bits (cheap, all lanes in step),
 // then evaluates only the samples whose cell is occupied, lowest first, so a
 // lane's evaluations do not wait for the empty stretches of other lanes.
+// FP32 compositing takes them two at a time: both samples' cells are
+// gathered together (those gathers mostly miss the L1, so two in flight hide
+// part of the wait), then the two are folded in order.
 //
 // Fewer gathers, fewer instructions.  The kernel is bound by the latency of
 // its gathers (the L1 misses above all) together with instruction issue, not
@@ -459,6 +462,11 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
       // multiply-add per sample); MIP compares decoded values with the
       // brick maximum and decodes each voxel
       constexpr bool FOLD = FMT == 2 && OP == 0;
+      // FP32 compositing evaluates its occupied samples two at a time (its
+      // gathers miss the L1 most; 1.305 -> 1.229 ms on the bench orbit); the
+      // narrower forms, whose cells more often share cached lines, and maximum
+      // intensity projection, which then spills registers, one at a time
+      constexpr bool PAIRS = FMT == 0 && OP == 0;
       const float tsc = FOLD ? tf_scale * s_q : tf_scale, tbi = FOLD ? __builtin_fmaf(o_q, tf_scale, tf_bias) : tf_bias;
       // byte steps to the +y/+z neighbour: inside a micro-block, or across
       // into the next one (from its last row or slice)
@@ -544,73 +552,171 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
           int last = CHUNK - 1;
           for (int half = 0; half < CHUNK / 32; ++half) {
             uint32_t m32 = stop ? 0u : (uint32_t)(mask >> (32 * half));
-            while (m32) {
-              const int i = 32 * half + (int)__builtin_ctz(m32);
-              m32 &= m32 - 1u;
-              const float fi = (float)i;
-              const float ux = __builtin_fmaf(fi, sfx, fx0), uy = __builtin_fmaf(fi, sfy, fy0),
-                          uz = __builtin_fmaf(fi, sfz, fz0);
-              const float wx = __builtin_amdgcn_fractf(ux), wy = __builtin_amdgcn_fractf(uy),
-                          wz = __builtin_amdgcn_fractf(uz);
-              // the sample's cell (inside the brick: 0 <= ix, iy, iz < 2^24)
-              const uint32_t ix = (uint32_t)(bx + floor_i32(ux)), iy = (uint32_t)(by + floor_i32(uy)),
-                             iz = (uint32_t)(bz + floor_i32(uz));
-              const int ry = (int)(iy & 3u), rz = (int)(iz & 3u);
-              const uint32_t a000 = (uint32_t)mad_i24(
-                  rz, rzb, mad_i24(ry, ryb, mad_i24((int)(ix & 3u), rxb,
-                                                    (int)mad_u24(ix, cxb, mad_u24(iy, cyb, __umul24(iz, czb))))));
-              // the 8 voxels of the sample's cell, loaded only when the cell
-              // differs from the one the lane interpolated last
-              if (a000 != cell_ofs) {
-                const uint32_t dy = ry == 3 ? dyb : (BC_ROW << sh);
-                const uint32_t dz = rz == 3 ? dzb : ((4u * BC_ROW) << sh);
-                const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
-                load_pair<FOLD ? 3 : FMT>(pool, a000, s_q, o_q, cv[0], cv[1]);
-                load_pair<FOLD ? 3 : FMT>(pool, a010, s_q, o_q, cv[2], cv[3]);
-                load_pair<FOLD ? 3 : FMT>(pool, a001, s_q, o_q, cv[4], cv[5]);
-                load_pair<FOLD ? 3 : FMT>(pool, a011, s_q, o_q, cv[6], cv[7]);
-                cell_ofs = a000;
+            if constexpr (PAIRS) {
+              // occupied samples two at a time: both cells' gathers in flight
+              // together (the second sample's only if its cell differs from the
+              // first's), then the samples folded in order; the arithmetic of
+              // each sample is that of one taken alone
+              while (m32) {
+                const int i0 = 32 * half + (int)__builtin_ctz(m32);
+                m32 &= m32 - 1u;
+                const bool two = m32 != 0u;
+                const int i1 = two ? 32 * half + (int)__builtin_ctz(m32) : i0;
+                if (two) m32 &= m32 - 1u;
+                float w0[3], w1[3];
+                uint32_t a0, a1;
+                int ry0, rz0, ry1, rz1;
+                auto cell = [&](int i, float* w, uint32_t& a, int& ry, int& rz) {
+                  const float fi = (float)i;
+                  const float ux = __builtin_fmaf(fi, sfx, fx0), uy = __builtin_fmaf(fi, sfy, fy0),
+                              uz = __builtin_fmaf(fi, sfz, fz0);
+                  w[0] = __builtin_amdgcn_fractf(ux);
+                  w[1] = __builtin_amdgcn_fractf(uy);
+                  w[2] = __builtin_amdgcn_fractf(uz);
+                  const uint32_t ix = (uint32_t)(bx + floor_i32(ux)), iy = (uint32_t)(by + floor_i32(uy)),
+                                 iz = (uint32_t)(bz + floor_i32(uz));
+                  ry = (int)(iy & 3u);
+                  rz = (int)(iz & 3u);
+                  a = (uint32_t)mad_i24(rz, rzb, mad_i24(ry, ryb, mad_i24((int)(ix & 3u), rxb,
+                                        (int)mad_u24(ix, cxb, mad_u24(iy, cyb, __umul24(iz, czb))))));
+                };
+                auto gather = [&](uint32_t a, int ry, int rz, float* v) {
+                  const uint32_t dy = ry == 3 ? dyb : (BC_ROW << sh);
+                  const uint32_t dz = rz == 3 ? dzb : ((4u * BC_ROW) << sh);
+                  const uint32_t a010 = a + dy, a001 = a + dz, a011 = a001 + dy;
+                  load_pair<FOLD ? 3 : FMT>(pool, a, s_q, o_q, v[0], v[1]);
+                  load_pair<FOLD ? 3 : FMT>(pool, a010, s_q, o_q, v[2], v[3]);
+                  load_pair<FOLD ? 3 : FMT>(pool, a001, s_q, o_q, v[4], v[5]);
+                  load_pair<FOLD ? 3 : FMT>(pool, a011, s_q, o_q, v[6], v[7]);
+                };
+                cell(i0, w0, a0, ry0, rz0);
+                cell(i1, w1, a1, ry1, rz1);
+                if (a0 != cell_ofs) {
+                  gather(a0, ry0, rz0, cv);
+                  cell_ofs = a0;
+                }
+                float cw[8];
+                const bool own1 = two && a1 != a0;
+                if (own1) gather(a1, ry1, rz1, cw);
+                auto sample = [&](const float* v, const float* w, int i) {
+                  const float c00 = __builtin_fmaf(w[0], v[1] - v[0], v[0]);
+                  const float c10 = __builtin_fmaf(w[0], v[3] - v[2], v[2]);
+                  const float c01 = __builtin_fmaf(w[0], v[5] - v[4], v[4]);
+                  const float c11 = __builtin_fmaf(w[0], v[7] - v[6], v[6]);
+                  const float c0 = __builtin_fmaf(w[1], c10 - c00, c00);
+                  const float c1 = __builtin_fmaf(w[1], c11 - c01, c01);
+                  const float val = __builtin_fmaf(w[2], c1 - c0, c0);
+                  if (OP == 1) {
+                    mx = fmaxf(mx, val);
+                    if (mx >= bound) {
+                      last = i;
+                      stop = true;
+                      m32 = 0u;
+                    }
+                    return;
+                  }
+                  const float xt = __builtin_amdgcn_fmed3f(__builtin_fmaf(val, tsc, tbi), 0.0f, kmax_f);
+                  const int it = TF_LDS ? (int)xt : min((int)xt, K - 2);
+                  const float ft = TF_LDS ? __builtin_amdgcn_fractf(xt) : xt - (float)it;
+                  float4 q0, dq;
+                  if (TF_LDS) {
+                    q0 = s_tab[2 * it];
+                    dq = s_tab[2 * it + 1];
+                  } else {
+                    q0 = gtab[it];
+                    const float4 q1 = gtab[it + 1];
+                    dq = make_float4(q1.x - q0.x, q1.y - q0.y, q1.z - q0.z, q1.w - q0.w);
+                  }
+                  const float om = 1.0f - acc.w;
+                  acc.x = __builtin_fmaf(om, __builtin_fmaf(ft, dq.x, q0.x), acc.x);
+                  acc.y = __builtin_fmaf(om, __builtin_fmaf(ft, dq.y, q0.y), acc.y);
+                  acc.z = __builtin_fmaf(om, __builtin_fmaf(ft, dq.z, q0.z), acc.z);
+                  acc.w = __builtin_fmaf(om, __builtin_fmaf(ft, dq.w, q0.w), acc.w);
+                  if (acc.w >= tau) {
+                    last = i;
+                    stop = true;
+                    m32 = 0u;
+                  }
+                };
+                sample(cv, w0, i0);
+                if (two && !stop) {
+                  if (own1) {
+  #pragma unroll
+                    for (int q = 0; q < 8; ++q) cv[q] = cw[q];
+                    cell_ofs = a1;
+                  }
+                  sample(cv, w1, i1);
+                }
               }
-              const float c00 = __builtin_fmaf(wx, cv[1] - cv[0], cv[0]);
-              const float c10 = __builtin_fmaf(wx, cv[3] - cv[2], cv[2]);
-              const float c01 = __builtin_fmaf(wx, cv[5] - cv[4], cv[4]);
-              const float c11 = __builtin_fmaf(wx, cv[7] - cv[6], cv[6]);
-              const float c0 = __builtin_fmaf(wy, c10 - c00, c00);
-              const float c1 = __builtin_fmaf(wy, c11 - c01, c01);
-              const float val = __builtin_fmaf(wz, c1 - c0, c0);
-              if (OP == 1) {
-                mx = fmaxf(mx, val);
-                if (mx >= bound) {
+            } else {
+              while (m32) {
+                const int i = 32 * half + (int)__builtin_ctz(m32);
+                m32 &= m32 - 1u;
+                const float fi = (float)i;
+                const float ux = __builtin_fmaf(fi, sfx, fx0), uy = __builtin_fmaf(fi, sfy, fy0),
+                            uz = __builtin_fmaf(fi, sfz, fz0);
+                const float wx = __builtin_amdgcn_fractf(ux), wy = __builtin_amdgcn_fractf(uy),
+                            wz = __builtin_amdgcn_fractf(uz);
+                // the sample's cell (inside the brick: 0 <= ix, iy, iz < 2^24)
+                const uint32_t ix = (uint32_t)(bx + floor_i32(ux)), iy = (uint32_t)(by + floor_i32(uy)),
+                               iz = (uint32_t)(bz + floor_i32(uz));
+                const int ry = (int)(iy & 3u), rz = (int)(iz & 3u);
+                const uint32_t a000 = (uint32_t)mad_i24(
+                    rz, rzb, mad_i24(ry, ryb, mad_i24((int)(ix & 3u), rxb,
+                                                      (int)mad_u24(ix, cxb, mad_u24(iy, cyb, __umul24(iz, czb))))));
+                // the 8 voxels of the sample's cell, loaded only when the cell
+                // differs from the one the lane interpolated last
+                if (a000 != cell_ofs) {
+                  const uint32_t dy = ry == 3 ? dyb : (BC_ROW << sh);
+                  const uint32_t dz = rz == 3 ? dzb : ((4u * BC_ROW) << sh);
+                  const uint32_t a010 = a000 + dy, a001 = a000 + dz, a011 = a001 + dy;
+                  load_pair<FOLD ? 3 : FMT>(pool, a000, s_q, o_q, cv[0], cv[1]);
+                  load_pair<FOLD ? 3 : FMT>(pool, a010, s_q, o_q, cv[2], cv[3]);
+                  load_pair<FOLD ? 3 : FMT>(pool, a001, s_q, o_q, cv[4], cv[5]);
+                  load_pair<FOLD ? 3 : FMT>(pool, a011, s_q, o_q, cv[6], cv[7]);
+                  cell_ofs = a000;
+                }
+                const float c00 = __builtin_fmaf(wx, cv[1] - cv[0], cv[0]);
+                const float c10 = __builtin_fmaf(wx, cv[3] - cv[2], cv[2]);
+                const float c01 = __builtin_fmaf(wx, cv[5] - cv[4], cv[4]);
+                const float c11 = __builtin_fmaf(wx, cv[7] - cv[6], cv[6]);
+                const float c0 = __builtin_fmaf(wy, c10 - c00, c00);
+                const float c1 = __builtin_fmaf(wy, c11 - c01, c01);
+                const float val = __builtin_fmaf(wz, c1 - c0, c0);
+                if (OP == 1) {
+                  mx = fmaxf(mx, val);
+                  if (mx >= bound) {
+                    last = i;
+                    stop = true;
+                    m32 = 0u;
+                  }
+                  continue;
+                }
+                // clamp to [0, K-1] (the median of three, exact)
+                const float xt = __builtin_amdgcn_fmed3f(__builtin_fmaf(val, tsc, tbi), 0.0f, kmax_f);
+                // (the table in LDS has an entry K-1 with a zero difference)
+                const int it = TF_LDS ? (int)xt : min((int)xt, K - 2);
+                const float ft = TF_LDS ? __builtin_amdgcn_fractf(xt) : xt - (float)it;
+                // table entry and its difference to the next entry
+                float4 q0, dq;
+                if (TF_LDS) {
+                  q0 = s_tab[2 * it];
+                  dq = s_tab[2 * it + 1];
+                } else {
+                  q0 = gtab[it];
+                  const float4 q1 = gtab[it + 1];
+                  dq = make_float4(q1.x - q0.x, q1.y - q0.y, q1.z - q0.z, q1.w - q0.w);
+                }
+                const float om = 1.0f - acc.w;
+                acc.x = __builtin_fmaf(om, __builtin_fmaf(ft, dq.x, q0.x), acc.x);
+                acc.y = __builtin_fmaf(om, __builtin_fmaf(ft, dq.y, q0.y), acc.y);
+                acc.z = __builtin_fmaf(om, __builtin_fmaf(ft, dq.z, q0.z), acc.z);
+                acc.w = __builtin_fmaf(om, __builtin_fmaf(ft, dq.w, q0.w), acc.w);
+                if (acc.w >= tau) {
                   last = i;
                   stop = true;
                   m32 = 0u;
                 }
-                continue;
-              }
-              // clamp to [0, K-1] (the median of three, exact)
-              const float xt = __builtin_amdgcn_fmed3f(__builtin_fmaf(val, tsc, tbi), 0.0f, kmax_f);
-              // (the table in LDS has an entry K-1 with a zero difference)
-              const int it = TF_LDS ? (int)xt : min((int)xt, K - 2);
-              const float ft = TF_LDS ? __builtin_amdgcn_fractf(xt) : xt - (float)it;
-              // table entry and its difference to the next entry
-              float4 q0, dq;
-              if (TF_LDS) {
-                q0 = s_tab[2 * it];
-                dq = s_tab[2 * it + 1];
-              } else {
-                q0 = gtab[it];
-                const float4 q1 = gtab[it + 1];
-                dq = make_float4(q1.x - q0.x, q1.y - q0.y, q1.z - q0.z, q1.w - q0.w);
-              }
-              const float om = 1.0f - acc.w;
-              acc.x = __builtin_fmaf(om, __builtin_fmaf(ft, dq.x, q0.x), acc.x);
-              acc.y = __builtin_fmaf(om, __builtin_fmaf(ft, dq.y, q0.y), acc.y);
-              acc.z = __builtin_fmaf(om, __builtin_fmaf(ft, dq.z, q0.z), acc.z);
-              acc.w = __builtin_fmaf(om, __builtin_fmaf(ft, dq.w, q0.w), acc.w);
-              if (acc.w >= tau) {
-                last = i;
-                stop = true;
-                m32 = 0u;
               }
             }
           }
