@@ -62,24 +62,38 @@ __device__ __forceinline__ df df_mul_f(df a, float b) {
   return fast_two_sum(p.hi, p.lo);
 }
 
+// a + b for a float b: the leading parts summed exactly, the trailing part
+// added to the error once
+__device__ __forceinline__ df df_add_f(df a, float b) {
+#pragma clang fp contract(off)
+  df s = two_sum(a.hi, b);
+  s.lo = s.lo + a.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+// a / b: quotient digits from the hardware reciprocal of b.hi (about 1 ulp),
+// each taken against the exact remainder, so that the approximate reciprocal
+// costs no accuracy; b.hi is a normal number at the call sites (ray
+// directions and lengths of order one)
 __device__ __forceinline__ df df_div(df a, df b) {
 #pragma clang fp contract(off)
-  float q1 = a.hi / b.hi;
+  const float rb = __builtin_amdgcn_rcpf(b.hi);
+  float q1 = a.hi * rb;
   df r = df_sub(a, df_mul_f(b, q1));
-  float q2 = r.hi / b.hi;
+  float q2 = r.hi * rb;
   r = df_sub(r, df_mul_f(b, q2));
-  float q3 = r.hi / b.hi;
+  float q3 = r.hi * rb;
   df q = fast_two_sum(q1, q2);
-  return df_add(q, df_from(q3));
+  return df_add_f(q, q3);
 }
 
 __device__ __forceinline__ df df_sqrt(df a) {
 #pragma clang fp contract(off)
   if (a.hi <= 0.0f) return df_from(0.0f);
-  float x = __builtin_sqrtf(a.hi);
+  float x = __builtin_amdgcn_sqrtf(a.hi);   // about 1 ulp; the correction below refines it
   df x2 = two_prod(x, x);
   df r = df_sub(a, x2);
-  float c = r.hi / (2.0f * x);
+  float c = r.hi * (0.5f * __builtin_amdgcn_rcpf(x));
   return fast_two_sum(x, c);
 }
 

@@ -241,22 +241,15 @@ __global__ __launch_bounds__(256) void classify_kernel(ClassifyArgs a) {
 // ------------------------------------------------------------------ rays
 __device__ __forceinline__ df dfv(float hi, float lo) { return df_make(hi, lo); }
 
-// smallest j >= 0 with t_in + (j + 1/2) dt >= t (estimate with 1/dt, then an
-// exact fix-up against the sample-time formula)
-__device__ __forceinline__ int first_index(df t_in, df dt, df idt, df t) {
+// smallest j >= 0 with t_in + (j + 1/2) dt >= t, that is ceil(q - 1/2) for
+// q = (t - t_in) / dt, taken exactly from the double-float q: q.hi - 1/2 is
+// exact, and unless it is an integer the trailing part (below half its ulp)
+// cannot carry it past one
+__device__ __forceinline__ int first_index(df t_in, df idt, df t) {
   const df q = df_mul(df_sub(t, t_in), idt);
-  float jf = ceilf(df_to_f(q) - 0.5f);
-  int j = (int)fmaxf(jf, 0.0f);
-  for (int it = 0; it < 3; ++it) {
-    const df tj = df_add(t_in, df_mul(df_from((float)j + 0.5f), dt));
-    if (df_lt(tj, t)) { ++j; continue; }
-    if (j > 0) {
-      const df tm = df_add(t_in, df_mul(df_from((float)j - 0.5f), dt));
-      if (df_ge(tm, t)) { --j; continue; }
-    }
-    break;
-  }
-  return j;
+  const float c = q.hi - 0.5f;
+  const float j = ceilf(c);
+  return (int)fmaxf((j == c && q.lo > 0.0f) ? j + 1.0f : j, 0.0f);
 }
 
 struct Slab { df t0, t1; bool miss; };
@@ -273,8 +266,8 @@ __device__ __forceinline__ Slab slab_df(const df* o, const df* d, const df* id, 
       if (!in) s.miss = true;
       continue;
     }
-    const df ta = df_mul(df_sub(df_from(lo[a]), o[a]), id[a]);
-    const df tb = df_mul(df_sub(df_from(hi[a]), o[a]), id[a]);
+    const df ta = df_mul(df_add_f(df_neg(o[a]), lo[a]), id[a]);
+    const df tb = df_mul(df_add_f(df_neg(o[a]), hi[a]), id[a]);
     s.t0 = df_max(s.t0, df_min(ta, tb));
     s.t1 = df_min(s.t1, df_max(ta, tb));
   }
@@ -302,8 +295,8 @@ __device__ __forceinline__ df df_abs(df a) { return df_lt(a, df_from(0.0f)) ? df
 __device__ bool ray_segment(const BcViewParams& vp, const int32_t* gdims, const BcBrick& br, int px, int py,
                             bool per_voxel, RaySeg& seg) {
   const int W = vp.width, H = vp.height;
-  const df x = df_mul(df_from((float)(2 * px + 1 - W)), dfv(vp.iw_hi, vp.iw_lo));
-  const df y = df_mul(df_from((float)(H - 2 * py - 1)), dfv(vp.ih_hi, vp.ih_lo));
+  const df x = df_mul_f(dfv(vp.iw_hi, vp.iw_lo), (float)(2 * px + 1 - W));
+  const df y = df_mul_f(dfv(vp.ih_hi, vp.ih_lo), (float)(H - 2 * py - 1));
   df o[3], d[3], id[3];
   if (vp.kind == 0) {
     df u[3];
@@ -338,17 +331,17 @@ __device__ bool ray_segment(const BcViewParams& vp, const int32_t* gdims, const 
     idt = df_max(df_max(df_abs(d[0]), df_abs(d[1])), df_abs(d[2]));
     dt = df_div(df_from(1.0f), idt);
   }
-  const int n = first_index(t_in, dt, idt, g.t1);
-  int j0 = (b.t0.hi == -INFINITY) ? 0 : first_index(t_in, dt, idt, b.t0);
-  int j1 = (b.t1.hi == INFINITY) ? n : first_index(t_in, dt, idt, b.t1);
+  const int n = first_index(t_in, idt, g.t1);
+  int j0 = (b.t0.hi == -INFINITY) ? 0 : first_index(t_in, idt, b.t0);
+  int j1 = (b.t1.hi == INFINITY) ? n : first_index(t_in, idt, b.t1);
   j0 = min(j0, n);
   j1 = min(max(j1, j0), n);
   if (j1 <= j0) return false;
   seg.n = j1 - j0;
-  const df t0 = df_add(t_in, df_mul(df_from((float)j0 + 0.5f), dt));
+  const df t0 = df_add(t_in, df_mul_f(dt, (float)j0 + 0.5f));
   for (int a = 0; a < 3; ++a) {
     const df p = df_add(o[a], df_mul(t0, d[a]));
-    seg.u[a] = q32(df_sub(p, df_from((float)br.lo[a] - 0.5f)));
+    seg.u[a] = q32(df_add_f(p, 0.5f - (float)br.lo[a]));
     seg.s[a] = q32(df_mul(dt, d[a]));
   }
   return true;
