@@ -91,10 +91,11 @@ struct bc_ctx {
   size_t elem_bytes = 4, src_elem_bytes = 4;
   size_t bytes[4] = {0, 0, 0, 0};
   size_t off_bricks = 0, off_fin = 0, off_views = 0, off_order = 0, off_rects = 0, off_item_base = 0,
-         off_ctr = 0, off_occ = 0, off_item_perm = 0;
+         off_ctr = 0, off_occ = 0, off_item_perm = 0, off_item_entry = 0;
   // a second set of per-pass arrays, for a pass that runs concurrently with
   // another (the validation pass of a learned frame)
-  size_t off_views_b = 0, off_order_b = 0, off_rects_b = 0, off_item_base_b = 0, off_item_perm_b = 0, off_ctr_b = 0;
+  size_t off_views_b = 0, off_order_b = 0, off_rects_b = 0, off_item_base_b = 0, off_item_perm_b = 0,
+         off_item_entry_b = 0, off_ctr_b = 0;
   int max_occ_words = 0;
   void* dev[4] = {nullptr, nullptr, nullptr, nullptr};
   // per-frame input ring (pinned host memory, kPasses pass inputs per slot) and events
@@ -289,6 +290,7 @@ BcFramePtrs frame_ptrs(bc_ctx* c) {
   f.rects = reinterpret_cast<int32_t*>(meta + c->off_rects);
   f.item_base = reinterpret_cast<int32_t*>(meta + c->off_item_base);
   f.item_perm = reinterpret_cast<int32_t*>(meta + c->off_item_perm);
+  f.item_entry = reinterpret_cast<int4*>(meta + c->off_item_entry);
   f.n_queues = c->xcd_queues ? 8 : 1;
   f.ctr = reinterpret_cast<BcCounters*>(meta + c->off_ctr);
   f.sub = static_cast<float4*>(c->dev[2]);
@@ -387,6 +389,7 @@ BcFramePtrs second_slot(bc_ctx* c, BcFramePtrs f, float4* sub, int64_t first, in
   f.rects = reinterpret_cast<int32_t*>(meta + c->off_rects_b);
   f.item_base = reinterpret_cast<int32_t*>(meta + c->off_item_base_b);
   f.item_perm = reinterpret_cast<int32_t*>(meta + c->off_item_perm_b);
+  f.item_entry = reinterpret_cast<int4*>(meta + c->off_item_entry_b);
   f.ctr = reinterpret_cast<BcCounters*>(meta + c->off_ctr_b);
   f.sub = sub + first * 64;
   f.max_items = cap;
@@ -624,12 +627,14 @@ int bc_plan(bc_ctx* c, const bc_volume_desc* d, int max_views, int max_w, int ma
   c->off_rects = m; m = align256(m + sizeof(int32_t) * 4 * BC_MAX_VIEWS * c->n_bricks);
   c->off_item_base = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
   c->off_item_perm = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
+  c->off_item_entry = m; m = align256(m + sizeof(int4) * BC_MAX_VIEWS * c->n_bricks);
   c->off_ctr = m; m = align256(m + sizeof(BcCounters));
   c->off_views_b = m; m = align256(m + sizeof(BcViewParams) * BC_MAX_VIEWS);
   c->off_order_b = m; m = align256(m + sizeof(int32_t) * BC_MAX_VIEWS * c->n_bricks);
   c->off_rects_b = m; m = align256(m + sizeof(int32_t) * 4 * BC_MAX_VIEWS * c->n_bricks);
   c->off_item_base_b = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
   c->off_item_perm_b = m; m = align256(m + sizeof(int32_t) * (BC_MAX_VIEWS * c->n_bricks + 1));
+  c->off_item_entry_b = m; m = align256(m + sizeof(int4) * BC_MAX_VIEWS * c->n_bricks);
   c->off_ctr_b = m; m = align256(m + sizeof(BcCounters));
   c->off_occ = m; m = align256(m + sizeof(uint32_t) * (size_t)occ_words);
   c->bytes[1] = m;

@@ -368,6 +368,9 @@ __global__ __launch_bounds__(1024) void setup_kernel(BcFramePtrs f) {
     int b, v;
     queue_entry(k, nb, nv, Q, b, v);
     f.item_base[b * nv + v] = run;
+    const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
+    f.item_entry[k] = make_int4(b | (v << 16), sel_count(r[0], r[2], ts, tox), sel_first(r[0], ts, tox),
+                                sel_first(r[1], ts, toy));
     run += count_at(k);
   }
   __syncthreads();

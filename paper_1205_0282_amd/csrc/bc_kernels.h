@@ -31,6 +31,8 @@ struct BcFramePtrs {
   int32_t* rects;         // [BC_MAX_VIEWS][n_bricks][4] tiles (x0, y0, x1, y1)
   int32_t* item_base;     // [n_bricks * n_views + 1] first item of entry b * n_views + v
   int32_t* item_perm;     // [n_bricks * n_views + 1] first item of the entry at each queue-order position
+  int4* item_entry;       // [n_bricks * n_views] the entry at each queue-order position: brick | view << 16,
+                          // its selected tile columns, its first selected tile x and y
   BcCounters* ctr;
   float4* sub;            // sub-image tiles: [max_items][64] (one float per ray, read as
                           // float[max_items][64], for maximum intensity projection)

@@ -46,6 +46,16 @@
 #include "bc_types.h"
 #include "bc_kernels.h"
 #include "bc_df.h"
+
+// Launch data that no wave writes while the ray caster runs (frame inputs,
+// view and brick records, the queue tables), addressed in the constant address
+// space so that wave-uniform reads of it become scalar loads: they then wait on
+// the scalar counter, not behind the vector loads and atomics in flight.
+#define KC(T) const __attribute__((address_space(4))) T
+template <typename T> __device__ __forceinline__ KC(T)* kc(const T* p) { return (KC(T)*)p; }
+template <bool SCALAR, typename T> __device__ __forceinline__ auto rec(const T* p) {
+  if constexpr (SCALAR) return kc(p); else return p;
+}
 #include "bc_e4m3.h"
 
 namespace {
@@ -292,7 +302,8 @@ __device__ __forceinline__ df df_abs(df a) { return df_lt(a, df_from(0.0f)) ? df
 // is the view's, or with the per-voxel policy 1 / max_a |d_a| (consecutive
 // samples one voxel apart along the ray's dominant axis, the discrete ray
 // casting of Section 2.3.2).
-__device__ bool ray_segment(const BcViewParams& vp, const int32_t* gdims, const BcBrick& br, int px, int py,
+template <typename VP, typename BR>
+__device__ bool ray_segment(VP& vp, const int32_t* gdims, BR& br, int px, int py,
                             bool per_voxel, RaySeg& seg) {
   const int W = vp.width, H = vp.height;
   const df x = df_mul_f(dfv(vp.iw_hi, vp.iw_lo), (float)(2 * px + 1 - W));
@@ -366,8 +377,9 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   // table entry k at 2k, its difference to entry k+1 at 2k+1
   __shared__ float4 s_tab[(TF_LDS && OP == 0) ? 2 * BC_TF_LDS : 2];
   const int lane = threadIdx.x & 63;
-  const BcFrameIn* fin = f.fin;
-  if (f.ctr->n_items == 0) return;   // e.g. a conditional pass that is not needed
+  KC(BcFrameIn)* fin = kc(f.fin);
+  KC(BcCounters)* cr = kc(f.ctr);   // the lines the waves read, not the queue counters
+  if (cr->n_items == 0) return;   // e.g. a conditional pass that is not needed
   if (URGENT) __builtin_amdgcn_s_setprio(2);
   const int K = fin->K;
   const float tf_scale = fin->tf_scale;
@@ -375,7 +387,7 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   float tf_bias = fin->tf_bias;
   if (OP == 0) asm volatile("" : "+v"(tf_bias));
   const float kmax_f = (float)(K - 1);
-  const float4* gtab = reinterpret_cast<const float4*>(fin->table);
+  const float4* gtab = reinterpret_cast<const float4*>(f.fin->table);   // gathered per lane
   if (TF_LDS && OP == 0) {
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
       const float4 a = gtab[k], b = gtab[min(k + 1, K - 1)];
@@ -387,27 +399,27 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
 
   const int nv = f.n_views, nb = f.n_bricks;
   const int KB = nb * nv;
-  const uint32_t n_items = f.ctr->n_items;
+  const uint32_t n_items = cr->n_items;
   const bool ess = f.ess != 0;
   const bool per_voxel = f.step_policy != 0;
-  const int ts = fin->tile_stride, tox = fin->tile_ox, toy = fin->tile_oy;
+  const int ts = fin->tile_stride;
   constexpr uint32_t esz = FMT == 0 ? 4 : (FMT == 1 ? 2 : 1);
   // per-lane sample counts (a lane takes at most a few thousand samples per
   // item and a few dozen items per launch, far below 2^32)
   uint32_t nominal = 0, evaluated = 0;
   // queue of this workgroup's XCD first (workgroups are dispatched to the
   // XCDs round robin), then the others once it is drained
-  const BcCounters* cr = f.ctr;   // read-only lines
   const int Q = (int)cr->n_queues;
   int q = (int)(blockIdx.x % (unsigned)Q), drained = 0;
   uint32_t q_lo = cr->qbound[q], q_hi = cr->qbound[q + 1];
+  // a slot is claimed when the wave needs it: claiming one item ahead, the
+  // atomic in flight during the item before, made the launch 8% slower
   for (;;) {
     uint32_t item = 0;
     bool have = false;
     while (drained < Q) {
-      uint32_t it = 0;
-      if (lane == 0) it = atomicAdd(&f.ctr->q[q].next, 1u);
-      it = q_lo + __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+      const uint32_t claim = lane == 0 ? atomicAdd(&f.ctr->q[q].next, 1u) : 0u;
+      const uint32_t it = q_lo + (uint32_t)__builtin_amdgcn_readlane((int)claim, 0);
       if (it < q_hi && it < n_items) {
         item = it;
         have = true;
@@ -419,22 +431,25 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
       q_hi = cr->qbound[q + 1];
     }
     if (!have) break;
+    KC(int32_t)* perm = kc(f.item_perm);
     int lo = 0, hi = KB;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if ((uint32_t)f.item_perm[mid] <= item) lo = mid; else hi = mid;
+      if ((uint32_t)perm[mid] <= item) lo = mid; else hi = mid;
     }
-    int b, v;
-    queue_entry(lo, nb, nv, Q, b, v);
-    const int32_t* r = f.rects + ((int64_t)v * nb + b) * 4;
-    const int cx = sel_count(r[0], r[2], ts, tox);
-    const int local = (int)(item - (uint32_t)f.item_perm[lo]);
-    const int tx = sel_first(r[0], ts, tox) + (local % cx) * ts, ty = sel_first(r[1], ts, toy) + (local / cx) * ts;
-    const BcViewParams& vp = f.views[v];
+    KC(int4)& ent = kc(f.item_entry)[lo];
+    const int b = ent.x & 0xffff, v = ent.x >> 16, cx = ent.y;
+    const int local = (int)(item - (uint32_t)perm[lo]);
+    const int tx = ent.z + (local % cx) * ts, ty = ent.w + (local / cx) * ts;
+    // maximum intensity projection and compositing with the table in memory
+    // hold more wave-uniform values in their loops and, with the records as
+    // well, run out of scalar registers: they read them into vector registers
+    constexpr bool SREC = OP == 0 && TF_LDS;
+    auto& vp = rec<SREC>(f.views)[v];
     const int tsh = f.tile_shift;
     const int px = (tx << tsh) + (lane & ((1 << tsh) - 1));
     const int py = ty * (64 >> tsh) + (lane >> tsh);
-    const BcBrick& br = f.bricks[b];
+    auto& br = rec<SREC>(f.bricks)[b];
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     float mx = -INFINITY;
     RaySeg seg;
