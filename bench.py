@@ -72,21 +72,21 @@ ORBIT = 64
 # [options]` (the 64-frame orbit, twice).  Valid only for the kernel sources
 # whose SHA-256 is recorded; any other source reports null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "d332b888d98c1a05e5aa77db1e25a7f3539363712b48330435002e74754ceb37",
+    "sources_sha256": "70119b89d2ddaef879167c0750d2802e4095732830df1c744b7262bbf900f902",
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
-        "cube1024_persp1920x1080/f32/composite/fixed": 2297301823,
-        "cube1024_persp1920x1080/f16/composite/fixed": 1486305359,
-        "cube1024_persp1920x1080/fp8/composite/fixed": 1001427634,
-        "cube1024_persp1920x1080/f32/mip/voxel": 2480374387,
-        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 52093890540,
+        "cube1024_persp1920x1080/f32/composite/fixed": 2378673044,
+        "cube1024_persp1920x1080/f16/composite/fixed": 1529649388,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 1028811561,
+        "cube1024_persp1920x1080/f32/mip/voxel": 2549271208,
+        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 55991327779,
     },
     # L2 (TCC) hit rate over the same launches: TCC_HIT / (TCC_HIT + TCC_MISS)
     "l2_hit_rate": {
-        "cube1024_persp1920x1080/f32/composite/fixed": 0.7577,
-        "cube1024_persp1920x1080/f16/composite/fixed": 0.8027,
-        "cube1024_persp1920x1080/fp8/composite/fixed": 0.8196,
-        "cube1024_persp1920x1080/f32/mip/voxel": 0.7181,
-        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 0.6762,
+        "cube1024_persp1920x1080/f32/composite/fixed": 0.7600,
+        "cube1024_persp1920x1080/f16/composite/fixed": 0.8085,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 0.8266,
+        "cube1024_persp1920x1080/f32/mip/voxel": 0.6781,
+        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 0.6583,
     },
 }
 KERNEL_SOURCES = ("bc_render.hip", "bc_types.h", "bc_kernels.h", "bc_df.h", "bc_e4m3.h")

@@ -53,9 +53,6 @@
 // the scalar counter, not behind the vector loads and atomics in flight.
 #define KC(T) const __attribute__((address_space(4))) T
 template <typename T> __device__ __forceinline__ KC(T)* kc(const T* p) { return (KC(T)*)p; }
-template <bool SCALAR, typename T> __device__ __forceinline__ auto rec(const T* p) {
-  if constexpr (SCALAR) return kc(p); else return p;
-}
 #include "bc_e4m3.h"
 
 namespace {
@@ -302,8 +299,7 @@ __device__ __forceinline__ df df_abs(df a) { return df_lt(a, df_from(0.0f)) ? df
 // is the view's, or with the per-voxel policy 1 / max_a |d_a| (consecutive
 // samples one voxel apart along the ray's dominant axis, the discrete ray
 // casting of Section 2.3.2).
-template <typename VP, typename BR>
-__device__ bool ray_segment(VP& vp, const int32_t* gdims, BR& br, int px, int py,
+__device__ bool ray_segment(KC(BcViewParams)& vp, const int32_t* gdims, KC(BcBrick)& br, int px, int py,
                             bool per_voxel, RaySeg& seg) {
   const int W = vp.width, H = vp.height;
   const df x = df_mul_f(dfv(vp.iw_hi, vp.iw_lo), (float)(2 * px + 1 - W));
@@ -441,15 +437,11 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
     const int b = ent.x & 0xffff, v = ent.x >> 16, cx = ent.y;
     const int local = (int)(item - (uint32_t)perm[lo]);
     const int tx = ent.z + (local % cx) * ts, ty = ent.w + (local / cx) * ts;
-    // maximum intensity projection and compositing with the table in memory
-    // hold more wave-uniform values in their loops and, with the records as
-    // well, run out of scalar registers: they read them into vector registers
-    constexpr bool SREC = OP == 0 && TF_LDS;
-    auto& vp = rec<SREC>(f.views)[v];
+    KC(BcViewParams)& vp = kc(f.views)[v];
     const int tsh = f.tile_shift;
     const int px = (tx << tsh) + (lane & ((1 << tsh) - 1));
     const int py = ty * (64 >> tsh) + (lane >> tsh);
-    auto& br = rec<SREC>(f.bricks)[b];
+    KC(BcBrick)& br = kc(f.bricks)[b];
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     float mx = -INFINITY;
     RaySeg seg;
@@ -470,11 +462,12 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
       // multiply-add per sample); MIP compares decoded values with the
       // brick maximum and decodes each voxel
       constexpr bool FOLD = FMT == 2 && OP == 0;
-      // FP32 compositing evaluates its occupied samples two at a time (its
-      // gathers miss the L1 most; 1.305 -> 1.229 ms on the bench orbit); the
-      // narrower forms, whose cells more often share cached lines, and maximum
-      // intensity projection, which then spills registers, one at a time
-      constexpr bool PAIRS = FMT == 0 && OP == 0;
+      // FP32 evaluates its occupied samples two at a time (its gathers miss
+      // the L1 most; 1.305 -> 1.229 ms on the bench orbit, and 0.915 -> 0.879
+      // ms with maximum intensity projection at the per-voxel step); the
+      // narrower forms, whose cells more often share cached lines, one at a
+      // time, and so does projection with 64-sample chunks, which would spill
+      constexpr bool PAIRS = FMT == 0 && (OP == 0 || CHUNK == 32);
       const float tsc = FOLD ? tf_scale * s_q : tf_scale, tbi = FOLD ? __builtin_fmaf(o_q, tf_scale, tf_bias) : tf_bias;
       // byte steps to the +y/+z neighbour: inside a micro-block, or across
       // into the next one (from its last row or slice)
