@@ -406,9 +406,11 @@ __global__ __launch_bounds__(256, 4) void render_kernel(BcFramePtrs f) {
   // the queue of the XCD this workgroup runs on first, then the others once
   // it is drained; the XCD comes from its hardware id register (XCC_ID, bits
   // 0-3), not from the block index, so that the choice holds however the
-  // dispatcher deals workgroups to the XCDs (0.2% faster on the bench orbit)
+  // dispatcher deals workgroups to the XCDs (0.2% faster on the bench orbit).
+  // Q is 8 or 1, so Q - 1 masks the id to a queue (written without a branch,
+  // which left the projection kernels out of scalar registers)
   const int Q = (int)cr->n_queues;
-  int q = Q == 8 ? (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u) : 0, drained = 0;
+  int q = (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & (uint32_t)(Q - 1)), drained = 0;
   uint32_t q_lo = cr->qbound[q], q_hi = cr->qbound[q + 1];
   // a slot is claimed when the wave needs it: claiming one item ahead, the
   // atomic in flight during the item before, made the launch 8% slower
