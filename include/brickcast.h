@@ -131,15 +131,16 @@ typedef struct {
   double modelview[16];     /* rigid: [R t; 0 1] with R orthonormal (1e-9) */
   double projection[16];    /* perspective (row 3 = 0 0 -1 0) or orthographic (row 3 = 0 0 0 1) */
   int32_t width, height;
-  double step;              /* > 0, voxels */
+  double step;              /* > 0, voxels; at most 2^24 samples along the cube's diagonal */
   double ert_threshold;     /* in (0, 1]; 1 disables early termination */
 } bc_view;
 
 /* Set 1..4 views rendered together by the next frames (one launch renders all
  * of them).  All views must share width, height, step and ert_threshold, and
  * fit the planned max_views/max_w/max_h.  Copied.  Errors: BC_E_ARG for the
- * checks above; BC_E_NOMEM if the views' rendering rectangles need more
- * sub-image tiles than planned. */
+ * checks above (the step against the cube's diagonal once the context is
+ * planned; bc_render_frame checks views set before the plan); BC_E_NOMEM if
+ * the views' rendering rectangles need more sub-image tiles than planned. */
 int bc_set_view(bc_ctx* ctx, const bc_view* views, int n_views);
 
 /* Enqueue one frame on `stream` (a hipStream_t; NULL = the null stream) and
@@ -147,7 +148,9 @@ int bc_set_view(bc_ctx* ctx, const bc_view* views, int n_views);
  * float32, premultiplied RGBA (colour-mapped RGBA under BC_OP_MIP), 16-byte
  * aligned; pixels no brick covers are transparent black.  Errors (detected before anything is enqueued, `out`
  * untouched): BC_E_STATE if memory, bricks, transfer function or view is
- * missing; BC_E_ARG for a null or misaligned out. */
+ * missing; BC_E_ARG for a null or misaligned out, or a step (the view's, or a
+ * learned frame's coarse step) that takes more than 2^24 samples along the
+ * cube's diagonal. */
 int bc_render_frame(bc_ctx* ctx, float* out, void* stream);
 
 /* The same frame as bc_render_frame, for callers that cannot allocate (code
