@@ -131,7 +131,7 @@ typedef struct {
   double modelview[16];     /* rigid: [R t; 0 1] with R orthonormal (1e-9) */
   double projection[16];    /* perspective (row 3 = 0 0 -1 0) or orthographic (row 3 = 0 0 0 1) */
   int32_t width, height;
-  double step;              /* > 0, voxels; at most 2^24 samples along the cube's diagonal */
+  double step;              /* > 0, voxels; at most 2^22 samples along the cube's diagonal */
   double ert_threshold;     /* in (0, 1]; 1 disables early termination */
 } bc_view;
 
@@ -149,7 +149,7 @@ int bc_set_view(bc_ctx* ctx, const bc_view* views, int n_views);
  * aligned; pixels no brick covers are transparent black.  Errors (detected before anything is enqueued, `out`
  * untouched): BC_E_STATE if memory, bricks, transfer function or view is
  * missing; BC_E_ARG for a null or misaligned out, or a step (the view's, or a
- * learned frame's coarse step) that takes more than 2^24 samples along the
+ * learned frame's coarse step) that takes more than 2^22 samples along the
  * cube's diagonal. */
 int bc_render_frame(bc_ctx* ctx, float* out, void* stream);
 

@@ -198,12 +198,13 @@ double det4(const double* m) {
   return s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0;
 }
 
-// samples along the cube's diagonal at this step stay at most 2^24, so that
-// sample indices and counts are exact in FP32 and in 32-bit integers
+// samples along the cube's diagonal at this step stay at most 2^22, so that
+// sample indices are exact in FP32 with a fraction to spare (the ray caster
+// rounds half-sample times in FP32)
 bool step_fits(const bc_ctx* c, double step) {
   double d2 = 0.0;
   for (int a = 0; a < 3; ++a) d2 += (double)c->desc.global_dims[a] * (double)c->desc.global_dims[a];
-  return std::sqrt(d2) / step <= 16777216.0;
+  return std::sqrt(d2) / step <= 4194304.0;
 }
 
 int check_view(bc_ctx* c, const bc_view& v, int idx) {
@@ -211,7 +212,7 @@ int check_view(bc_ctx* c, const bc_view& v, int idx) {
     return fail(c, BC_E_ARG, "view %d: width/height %d x %d outside [1, 16384]", idx, v.width, v.height);
   if (!(is_fin(v.step) && v.step > 0.0)) return fail(c, BC_E_ARG, "view %d: step must be finite and > 0", idx);
   if (c->planned && !step_fits(c, v.step))
-    return fail(c, BC_E_ARG, "view %d: step %g takes more than 2^24 samples along the cube's diagonal", idx, v.step);
+    return fail(c, BC_E_ARG, "view %d: step %g takes more than 2^22 samples along the cube's diagonal", idx, v.step);
   if (!(v.ert_threshold > 0.0 && v.ert_threshold <= 1.0))
     return fail(c, BC_E_ARG, "view %d: ert_threshold must be in (0, 1]", idx);
   double M[16], P[16];
@@ -865,7 +866,7 @@ int render_impl(bc_ctx* c, float* out, void* stream, float4* sub, int64_t sub_ca
                 (long long)c->view_tiles, (long long)sub_cap);
   // (views set before the plan were not checked against the cube)
   if (!step_fits(c, c->views[0].step) || (c->learned && !step_fits(c, c->coarse_step)))
-    return fail(c, BC_E_ARG, "bc_render_frame: the step takes more than 2^24 samples along the cube's diagonal");
+    return fail(c, BC_E_ARG, "bc_render_frame: the step takes more than 2^22 samples along the cube's diagonal");
   const int n = (int)c->views.size();
   const int W = c->views[0].width, H = c->views[0].height;
   if (c->learned) {

@@ -46,6 +46,7 @@
 #include "bc_types.h"
 #include "bc_kernels.h"
 #include "bc_df.h"
+#include "bc_e4m3.h"
 
 // Launch data that no wave writes while the ray caster runs (frame inputs,
 // view and brick records, the queue tables), addressed in the constant address
@@ -53,7 +54,6 @@
 // the scalar counter, not behind the vector loads and atomics in flight.
 #define KC(T) const __attribute__((address_space(4))) T
 template <typename T> __device__ __forceinline__ KC(T)* kc(const T* p) { return (KC(T)*)p; }
-#include "bc_e4m3.h"
 
 namespace {
 
@@ -250,8 +250,9 @@ __device__ __forceinline__ df dfv(float hi, float lo) { return df_make(hi, lo); 
 
 // smallest j >= 0 with t_in + (j + 1/2) dt >= t, that is ceil(q - 1/2) for
 // q = (t - t_in) / dt, taken exactly from the double-float q: q.hi - 1/2 is
-// exact, and unless it is an integer the trailing part (below half its ulp)
-// cannot carry it past one
+// exact (q stays below 2^22: the boundary refuses steps with more samples
+// along the cube's diagonal), and unless it is an integer the trailing part
+// (below half its ulp) cannot carry it past one
 __device__ __forceinline__ int first_index(df t_in, df idt, df t) {
   const df q = df_mul(df_sub(t, t_in), idt);
   const float c = q.hi - 0.5f;

@@ -180,18 +180,18 @@ def test_view_tile_budget(lib, host_ctx):
 
 
 def test_step_bounded_by_the_cube_diagonal(lib, host_ctx):
-    """Once planned, a view whose step would take more than 2^24 samples along
-    the cube's diagonal is refused (sample indices stay exact)."""
+    """Once planned, a view whose step would take more than 2^22 samples along
+    the cube's diagonal is refused (sample indices stay exact in FP32)."""
     d = _desc()
     rc, _ = _plan(lib, host_ctx, d, views=1, w=64, h_=64, tiles=0)
     assert rc == 0
     diag = float(np.linalg.norm(np.asarray(d.global_dims[:], np.float64)))
     v = synth.orbit_view((64, 64, 64), 3, kind="persp", width=64, height=64)
-    v.step = diag / 2 ** 24 * 1.01
+    v.step = diag / 2 ** 22 * 1.01
     assert lib.bc_set_view(host_ctx, _views(v), 1) == 0
-    v.step = diag / 2 ** 24 * 0.99
+    v.step = diag / 2 ** 22 * 0.99
     assert lib.bc_set_view(host_ctx, _views(v), 1) == binding.BC_E_ARG
-    assert b"2^24" in lib.bc_last_error(host_ctx)
+    assert b"2^22" in lib.bc_last_error(host_ctx)
 
 
 def test_host_only_context_refuses_gpu_calls(lib, host_ctx):
