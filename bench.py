@@ -72,21 +72,21 @@ ORBIT = 64
 # [options]` (the 64-frame orbit, twice).  Valid only for the kernel sources
 # whose SHA-256 is recorded; any other source reports null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "fc8ffd7cad8d74c0601c345dd94c0c35185f8af8960bb36655a1d4cfbf8b6384",
+    "sources_sha256": "767e94236e551325df5546ab4f23daecb7fa462b135a0d3dbcbd0212cd0f23b7",
     "bytes": {   # "workload/storage/operator/step policy" -> bytes per launch
-        "cube1024_persp1920x1080/f32/composite/fixed": 2378576580,
-        "cube1024_persp1920x1080/f16/composite/fixed": 1530382305,
-        "cube1024_persp1920x1080/fp8/composite/fixed": 1028891259,
-        "cube1024_persp1920x1080/f32/mip/voxel": 2547106733,
-        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 56024032740,
+        "cube1024_persp1920x1080/f32/composite/fixed": 2379458324,
+        "cube1024_persp1920x1080/f16/composite/fixed": 1530188545,
+        "cube1024_persp1920x1080/fp8/composite/fixed": 1029400961,
+        "cube1024_persp1920x1080/f32/mip/voxel": 2545890382,
+        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 55999454989,
     },
     # L2 (TCC) hit rate over the same launches: TCC_HIT / (TCC_HIT + TCC_MISS)
     "l2_hit_rate": {
-        "cube1024_persp1920x1080/f32/composite/fixed": 0.7600,
+        "cube1024_persp1920x1080/f32/composite/fixed": 0.7599,
         "cube1024_persp1920x1080/f16/composite/fixed": 0.8084,
         "cube1024_persp1920x1080/fp8/composite/fixed": 0.8265,
-        "cube1024_persp1920x1080/f32/mip/voxel": 0.6783,
-        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 0.6581,
+        "cube1024_persp1920x1080/f32/mip/voxel": 0.6784,
+        "cube3000x3000x1500_f16_4views/f16/composite/fixed": 0.6583,
     },
 }
 KERNEL_SOURCES = ("bc_render.hip", "bc_types.h", "bc_kernels.h", "bc_df.h", "bc_e4m3.h")
